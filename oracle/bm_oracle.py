@@ -1,0 +1,182 @@
+"""FP64 CPU oracle for block matching (BM) -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may import this
+module. The product path (the HIP library and its Python binding) never calls it and
+shares no code with it.
+
+What it computes is the plain definition of block matching, written out slowly:
+
+* Euclidean BM (Sec. III-A, Eq. ``equ:bm`` with the metric of Eq. ``equ:bmMetric_app``):
+  for every reference patch X_i, the distance to a candidate X_j is the per-pair
+  subtraction sum_{c,l,m} (X_j - X_i)^2, evaluated in float64; the K candidates with the
+  smallest distance form the set S_i, |S_i| <= K.
+* Multi-channel patches are joint sqrt(n) x sqrt(n) x p blocks and the distance sums over
+  channels (Sec. IV, the channel sum S(.) of Eq. ``equ:self-convMM``).
+* The candidates of X_i are the patches inside its search window Omega_i (footnote to
+  Eq. ``eq:unifySelfConv``).
+
+Readings taken where the paper is silent (each one is listed in the design notes):
+
+* the window of side Wn (odd) holds the candidate top-left offsets (dy, dx) in
+  [-r, r]^2, r = (Wn - 1) / 2, so N_s = Wn^2 candidates away from borders;
+* at image borders the window is intersected with the valid positions, never shifted;
+* references sit on the grid {0, s, 2s, ...} in each axis (the last row/column is not
+  forced in); candidates use stride 1 (all overlapping patches);
+* a reference is its own candidate (distance 0; Sec. IV footnote on the group order);
+* ties are broken by the candidate's linear index j = qy * W + qx, i.e. the result is
+  the first K entries of the candidates sorted by the key (d, j);
+* fewer than K candidates: the row is padded with index -1 and distance +inf.
+
+Parity status: every function below is pinned by the CPU test suite against hand-checked
+values, closed forms, library routines or brute force (see tests/test_oracle_pins.py).
+"""
+from __future__ import annotations
+
+import numpy as np
+from numpy.lib.stride_tricks import sliding_window_view
+
+PAD_INDEX = -1
+
+
+# --------------------------------------------------------------------------------------
+# Geometry (readings: reference grid, clipped window)
+# --------------------------------------------------------------------------------------
+def valid_extent(H: int, W: int, P: int):
+    """Number of valid patch positions per axis: sqrt(M) = sqrt(N) - sqrt(n) + 1 (Eq. eq:selfConv)."""
+    return H - P + 1, W - P + 1
+
+
+def ref_positions(H: int, W: int, P: int, s: int):
+    """Reference top-left rows and columns on the stride-s grid {0, s, 2s, ...}."""
+    Hv, Wv = valid_extent(H, W, P)
+    return np.arange(0, Hv, s), np.arange(0, Wv, s)
+
+
+def ref_list(H: int, W: int, P: int, s: int):
+    """All references in row-major grid order as an (n_ref, 2) array of (ry, rx)."""
+    ys, xs = ref_positions(H, W, P, s)
+    yy, xx = np.meshgrid(ys, xs, indexing="ij")
+    return np.stack([yy.ravel(), xx.ravel()], axis=1)
+
+
+def window_box(ry: int, rx: int, Hv: int, Wv: int, Wn: int):
+    """Inclusive candidate box of reference (ry, rx): the Wn x Wn offsets clipped to the image."""
+    r = Wn // 2
+    return max(0, ry - r), min(Hv - 1, ry + r), max(0, rx - r), min(Wv - 1, rx + r)
+
+
+def candidate_count(H: int, W: int, P: int, s: int, Wn: int) -> int:
+    """Total number of (reference, candidate) pairs, by enumeration of every reference."""
+    Hv, Wv = valid_extent(H, W, P)
+    total = 0
+    for ry, rx in ref_list(H, W, P, s):
+        y0, y1, x0, x1 = window_box(int(ry), int(rx), Hv, Wv, Wn)
+        total += (y1 - y0 + 1) * (x1 - x0 + 1)
+    return total
+
+
+# --------------------------------------------------------------------------------------
+# Patch norms (h_X (.) h_X, Sec. III-B; used by Lemma 2)
+# --------------------------------------------------------------------------------------
+def patch_norms(x: np.ndarray, P: int) -> np.ndarray:
+    """Squared Frobenius norm of every valid patch, summed over channels, float64.
+
+    N[y, x] = sum_c sum_{l<P} sum_{m<P} X_c[y+l, x+m]^2 -- the entries of h_X (.) h_X.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    C, H, W = x.shape
+    Hv, Wv = valid_extent(H, W, P)
+    sq = x * x
+    out = np.zeros((Hv, Wv), dtype=np.float64)
+    for c in range(C):
+        for l in range(P):
+            for m in range(P):
+                out += sq[c, l:l + Hv, m:m + Wv]
+    return out
+
+
+# --------------------------------------------------------------------------------------
+# Distances by per-pair subtraction (Eq. equ:bmMetric_app)
+# --------------------------------------------------------------------------------------
+def pair_distance(x: np.ndarray, P: int, ry: int, rx: int, qy: int, qx: int) -> float:
+    """||X_j - X_i||_F^2 for reference (ry, rx) and candidate (qy, qx), float64."""
+    x = np.asarray(x, dtype=np.float64)
+    diff = x[:, qy:qy + P, qx:qx + P] - x[:, ry:ry + P, rx:rx + P]
+    return float(np.sum(diff * diff))
+
+
+def window_distances(x64: np.ndarray, P: int, Wn: int, ry: int, rx: int):
+    """All in-window distances of one reference.
+
+    Returns (d, j): float64 distances and int64 candidate indices j = qy*W + qx, both
+    flattened in row-major window order.
+    """
+    C, H, W = x64.shape
+    Hv, Wv = valid_extent(H, W, P)
+    y0, y1, x0, x1 = window_box(ry, rx, Hv, Wv, Wn)
+    region = x64[:, y0:y1 + P, x0:x1 + P]
+    cands = sliding_window_view(region, (P, P), axis=(1, 2))  # C, ny, nx, P, P
+    ref = x64[:, ry:ry + P, rx:rx + P]
+    diff = cands - ref[:, None, None, :, :]
+    d = np.sum(diff * diff, axis=(0, 3, 4))  # ny, nx
+    qy = np.arange(y0, y1 + 1)[:, None]
+    qx = np.arange(x0, x1 + 1)[None, :]
+    j = qy * W + qx
+    return d.ravel(), np.broadcast_to(j, d.shape).ravel().astype(np.int64)
+
+
+def select_k(d: np.ndarray, j: np.ndarray, K: int):
+    """The K smallest candidates under the key (d, j), padded with (-1, +inf)."""
+    order = np.lexsort((j, d))[:K]
+    idx = np.full(K, PAD_INDEX, dtype=np.int64)
+    dist = np.full(K, np.inf, dtype=np.float64)
+    idx[:order.size] = j[order]
+    dist[:order.size] = d[order]
+    return idx, dist
+
+
+def bm(x: np.ndarray, P: int, s: int, Wn: int, K: int, refs=None):
+    """Euclidean block matching (Eq. equ:bm), float64 brute force.
+
+    ``x`` is C x H x W (any real dtype; promoted exactly to float64). ``refs`` optionally
+    selects reference numbers (row-major grid order); by default every reference is done.
+    Returns (idx [n, K] int64, dist [n, K] float64), rows sorted ascending by (d, j).
+    """
+    x64 = np.asarray(x, dtype=np.float64)
+    if x64.ndim == 2:
+        x64 = x64[None]
+    C, H, W = x64.shape
+    rl = ref_list(H, W, P, s)
+    sel = np.arange(len(rl)) if refs is None else np.asarray(refs, dtype=np.int64)
+    idx = np.empty((len(sel), K), dtype=np.int64)
+    dist = np.empty((len(sel), K), dtype=np.float64)
+    for n, i in enumerate(sel):
+        ry, rx = int(rl[i, 0]), int(rl[i, 1])
+        d, j = window_distances(x64, P, Wn, ry, rx)
+        idx[n], dist[n] = select_k(d, j, K)
+    return idx, dist
+
+
+def bm_two_image(x: np.ndarray, y: np.ndarray, P: int, s: int, Wn: int, K: int):
+    """BM of the reference patches of ``x`` against candidate patches of ``y`` (same shape).
+
+    The windowed Self-Convolution X_{Omega_i} * X_i with the sub-image taken from a second
+    image; used to check offset recovery on shifted copies.
+    """
+    x64 = np.asarray(x, dtype=np.float64)
+    y64 = np.asarray(y, dtype=np.float64)
+    C, H, W = x64.shape
+    Hv, Wv = valid_extent(H, W, P)
+    rl = ref_list(H, W, P, s)
+    idx = np.empty((len(rl), K), dtype=np.int64)
+    dist = np.empty((len(rl), K), dtype=np.float64)
+    for n, (ry, rx) in enumerate(rl):
+        ry, rx = int(ry), int(rx)
+        y0, y1, x0, x1 = window_box(ry, rx, Hv, Wv, Wn)
+        cands = sliding_window_view(y64[:, y0:y1 + P, x0:x1 + P], (P, P), axis=(1, 2))
+        ref = x64[:, ry:ry + P, rx:rx + P]
+        diff = cands - ref[:, None, None, :, :]
+        d = np.sum(diff * diff, axis=(0, 3, 4))
+        j = (np.arange(y0, y1 + 1)[:, None] * W + np.arange(x0, x1 + 1)[None, :])
+        idx[n], dist[n] = select_k(d.ravel(), np.broadcast_to(j, d.shape).ravel(), K)
+    return idx, dist
