@@ -1,0 +1,151 @@
+/*
+ * bm.h -- C ABI of the MI355X block-matching library (libbm.so).
+ *
+ * Block matching (BM), Sec. III-A Eq. (equ:bm): for every reference patch X_i of an image,
+ * return the K candidate patches X_j of its search window with the smallest squared
+ * Euclidean distance ||X_j - X_i||_F^2.  The library evaluates each distance through
+ * Lemma 2 (Sec. III-B): d = ||X_j||^2 + ||X_i||^2 - 2 <X_i, X_j>, where the squared patch
+ * norms come from a box filter (the entries of h_X (.) h_X) and the inner products are the
+ * window-restricted Self-Convolution cross term C_i of Eq. (eq:selfConv), footnote to
+ * Eq. (eq:unifySelfConv).  Selection is Theorem 1 with the Euclidean H: the support of the
+ * K largest b_i = vec(C_i) - h_X(.)h_X / 2, i.e. the K smallest distances.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Image       planar C x H x W float32 (channel-major, then rows, then columns), device
+ *             memory, owned by the caller.  Multi-channel patches are joint P x P x C
+ *             blocks and distances sum over channels (Sec. IV, channel sum S(.)).
+ * References  top-left corners on the grid {0, s, 2s, ...} in each axis; n_ref =
+ *             (floor((H-P)/s)+1) * (floor((W-P)/s)+1), numbered row-major.
+ * Candidates  every valid patch position (stride 1) whose offset from the reference lies in
+ *             [-r, r]^2, r = (window-1)/2, intersected with the image (never shifted).
+ *             The reference is its own candidate (distance 0).
+ * Output      idx[i*K + k] = qy*W + qx (int32) and dist[i*K + k] (float32, clamped at 0),
+ *             sorted ascending by the key (dist, idx); rows with fewer than K candidates
+ *             are padded with idx = -1, dist = +inf.  Device memory, owned by the caller.
+ * Streams     `stream` is a hipStream_t passed as void* (NULL = the null stream).  Device
+ *             calls are asynchronous on that stream, like kernel launches.
+ * Errors      every call returns bm_status; BM_OK is 0.  Argument checks happen on the host
+ *             before anything is enqueued.  bm_last_error() returns a thread-local message
+ *             for the last failing call on the calling thread.
+ */
+#ifndef BM_H_
+#define BM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bm_status;
+#define BM_OK 0
+#define BM_EINVAL (-1)      /* invalid argument (the message names it)               */
+#define BM_ENOMEM (-2)      /* device or host allocation failed                       */
+#define BM_EDEVICE (-3)     /* HIP runtime error (launch, copy, no device)            */
+#define BM_EAGAIN (-4)      /* bm_poll: result not ready yet                          */
+#define BM_EBUSY (-5)       /* bm_submit: admission refused (budget or slots)         */
+#define BM_ENOTFOUND (-6)   /* unknown ticket                                          */
+#define BM_ECANCELED (-7)   /* ticket was cancelled                                    */
+#define BM_ENOTSUP (-8)     /* valid request outside what this build supports          */
+
+/* Arithmetic of the cross term <X_i, X_j>.  Norms and the distance assembly are float32
+ * in every form.  The split forms write x = hi + lo (hi = round(x), lo = round(x - hi)) and
+ * accumulate hi*hi + hi*lo + lo*hi in float32 on the matrix cores. */
+#define BM_PREC_FP32 0      /* float32 products, float32 accumulation                 */
+#define BM_PREC_BF16X3 1    /* bfloat16 hi/lo split, three products                   */
+#define BM_PREC_FP16X3 2    /* float16 hi/lo split after a power-of-two pre-scale     */
+
+/* bm_desc.flags */
+#define BM_FLAG_CENTER 1u   /* subtract a per-channel mean before the cross term (the
+                               distance is translation invariant; reduces cancellation) */
+
+/* One BM problem, following the paper's statement of BM: image, patch size sqrt(n),
+ * stride, search window, K (Sec. III-A; Sec. V-A fixes 6x6 patches, stride 1, 30x30). */
+typedef struct {
+  int32_t height, width, channels; /* image H, W, C; 1 <= C <= 8                        */
+  int32_t patch;                   /* patch side P, 1 <= P <= 16, P <= min(H, W)        */
+  int32_t stride;                  /* reference-grid stride s >= 1                      */
+  int32_t window;                  /* window side Wn, odd, >= 1                         */
+  int32_t k;                       /* neighbours kept, 1 <= K <= 64                     */
+  int32_t precision;               /* BM_PREC_*                                         */
+  uint32_t flags;                  /* BM_FLAG_*                                         */
+} bm_desc;
+
+typedef struct bm_plan_s* bm_plan_t;
+
+/* Validate `desc`, pick the kernel configuration for its shape (the autotuner's choice
+ * when a tuned entry exists, else the built-in rule), and allocate the plan-owned
+ * workspace on the current device.  Errors: BM_EINVAL (bad field), BM_ENOTSUP,
+ * BM_ENOMEM, BM_EDEVICE.  The plan is immutable afterwards. */
+bm_status bm_plan(const bm_desc* desc, bm_plan_t* out);
+
+/* Number of references, and the workspace bytes a caller must pass to bm_match to avoid
+ * the plan-owned one.  Either output pointer may be NULL. */
+bm_status bm_plan_info(bm_plan_t plan, int64_t* n_ref, int64_t* workspace_bytes);
+
+/* Run BM on one image: patch norms (box filter), then the fused cross-term / distance /
+ * top-K kernel.  d_img: C*H*W floats; d_idx, d_dist: n_ref*K each.  d_workspace: NULL to
+ * use the plan's own (then calls on one plan must not overlap in time), or
+ * workspace_bytes of device memory owned by the caller.  Asynchronous on `stream`. */
+bm_status bm_match(bm_plan_t plan, const float* d_img, int32_t* d_idx, float* d_dist,
+                   void* d_workspace, void* stream);
+
+/* Patch-norm map alone (the box filter, h_X (.) h_X of Sec. III-B): d_norm receives
+ * (H-P+1)*(W-P+1) floats, row-major.  Asynchronous on `stream`. */
+bm_status bm_norms(bm_plan_t plan, const float* d_img, float* d_norm, void* stream);
+
+/* Many images of uneven shapes in one persistent launch (plus one norm launch).  Entry b
+ * uses plans[b], d_imgs[b], d_idx[b], d_dist[b].  d_workspace must hold
+ * bm_batch_workspace() bytes or be NULL (then the library allocates and frees it inside
+ * the call, which synchronises `stream`). */
+bm_status bm_match_batch(int32_t n, const bm_plan_t* plans, const float* const* d_imgs,
+                         int32_t* const* d_idx, float* const* d_dist, void* d_workspace,
+                         void* stream);
+bm_status bm_batch_workspace(int32_t n, const bm_plan_t* plans, int64_t* bytes);
+
+bm_status bm_plan_destroy(bm_plan_t plan);
+
+/* ---- serving ---------------------------------------------------------------------- */
+typedef struct bm_server_s* bm_server_t;
+
+typedef struct {
+  int64_t hbm_budget_bytes;  /* device bytes the server may hold for admitted requests */
+  int32_t max_inflight;      /* admitted (device-resident) requests at most            */
+  int32_t max_queue;         /* queued, not yet admitted requests at most               */
+} bm_server_cfg;
+
+typedef struct {
+  double queue_s;   /* submit -> admitted                                             */
+  double device_s;  /* admitted -> result on the host                                  */
+  double total_s;   /* submit -> result ready                                          */
+  int64_t n_ref;
+} bm_request_stats;
+
+/* Start a server on the current device with its own scheduler thread and streams. */
+bm_status bm_server_create(const bm_server_cfg* cfg, bm_server_t* out);
+
+/* Queue one request; the host image (C*H*W floats) is copied before the call returns.
+ * BM_EBUSY when the queue is full or the request alone exceeds the device budget. */
+bm_status bm_submit(bm_server_t srv, const bm_desc* desc, const float* host_img,
+                    uint64_t* ticket);
+
+/* Non-blocking.  BM_EAGAIN while pending; BM_OK once done: copies n_ref*K results into
+ * the caller's host buffers (either may be NULL), fills stats (may be NULL) and retires
+ * the ticket.  BM_ENOTFOUND for unknown or retired tickets, BM_ECANCELED if cancelled. */
+bm_status bm_poll(bm_server_t srv, uint64_t ticket, int32_t* host_idx, float* host_dist,
+                  bm_request_stats* stats);
+
+/* Cancel a queued ticket (admitted work finishes and is discarded). */
+bm_status bm_cancel(bm_server_t srv, uint64_t ticket);
+
+/* Drain admitted work, stop the scheduler, free everything. */
+bm_status bm_server_destroy(bm_server_t srv);
+
+const char* bm_status_str(bm_status s);
+const char* bm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BM_H_ */

@@ -1,0 +1,207 @@
+// Host side of libbm.so: argument checks, plan geometry, workspace, kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/bm.h"
+#include "bm_internal.h"
+#include "plan.h"
+
+namespace bmk {
+
+hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* center,
+                       hipStream_t stream);
+
+static thread_local std::string g_err;
+
+bm_status fail(bm_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+bm_status hip_fail(hipError_t e, const char* what) {
+  return fail(BM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+const char* last_error() { return g_err.c_str(); }
+
+bm_status validate_desc(const bm_desc* d) {
+  if (!d) return fail(BM_EINVAL, "desc is NULL");
+  if (d->height < 1 || d->width < 1) return fail(BM_EINVAL, "height/width must be >= 1");
+  if (d->channels < 1 || d->channels > 8) return fail(BM_EINVAL, "channels must be in [1, 8]");
+  if (d->patch < 1 || d->patch > 16) return fail(BM_EINVAL, "patch must be in [1, 16]");
+  if (d->patch > d->height || d->patch > d->width)
+    return fail(BM_EINVAL, "patch %d larger than the image", d->patch);
+  if (d->stride < 1) return fail(BM_EINVAL, "stride must be >= 1");
+  if (d->window < 1 || (d->window & 1) == 0) return fail(BM_EINVAL, "window must be odd and >= 1");
+  if (d->k < 1 || d->k > kMaxK) return fail(BM_EINVAL, "k must be in [1, %d]", kMaxK);
+  if (d->precision < BM_PREC_FP32 || d->precision > BM_PREC_FP16X3)
+    return fail(BM_EINVAL, "unknown precision %d", d->precision);
+  if ((int64_t)d->height * d->width * d->channels >= (int64_t)1 << 31)
+    return fail(BM_EINVAL, "image too large for 32-bit indexing");
+  if (d->flags & ~BM_FLAG_CENTER) return fail(BM_EINVAL, "unknown flag bits 0x%x", d->flags);
+  const int pe = d->patch + (d->patch & 1);
+  if (d->channels * (pe / 2) * (pe / 2) > kMaxSteps)
+    return fail(BM_ENOTSUP, "channels * ceil(patch/2)^2 = %d exceeds %d",
+                d->channels * (pe / 2) * (pe / 2), kMaxSteps);
+  return BM_OK;
+}
+
+// Fill the launch geometry for a wave grid (wy x wx) and buffer capacity `cap`.
+void fill_geom(const bm_desc& d, int wy, int wx, int cap, XcGeom& g) {
+  memset(&g, 0, sizeof(g));
+  g.H = d.height;
+  g.W = d.width;
+  g.C = d.channels;
+  g.P = d.patch;
+  g.Pe = d.patch + (d.patch & 1);
+  g.s = d.stride;
+  g.r = d.window / 2;
+  g.K = d.k;
+  g.Hv = d.height - d.patch + 1;
+  g.Wv = d.width - d.patch + 1;
+  g.nry = (d.height - d.patch) / d.stride + 1;
+  g.nrx = (d.width - d.patch) / d.stride + 1;
+  g.WY = wy;
+  g.WX = wx;
+  g.nwg_y = (g.nry + kRefBlock * wy - 1) / (kRefBlock * wy);
+  g.nwg_x = (g.nrx + kRefBlock * wx - 1) / (kRefBlock * wx);
+  g.nwg_total = g.nwg_y * g.nwg_x;
+  const int span = 3 * g.s + 2 * g.r + 1;  // candidate positions across a 4-reference block
+  g.NT = (span + kTileN - 1) / kTileN;
+  g.NH = 4 * g.s * (wy - 1) + span;
+  g.NW = 4 * g.s * (wx - 1) + kTileN * g.NT;
+  g.NRS = g.NW;
+  g.SH = g.NH + g.Pe - 1;
+  g.SW = g.NW + g.Pe - 1;
+  g.RS = g.SW;
+  g.PLANE = g.SH * g.RS;
+  g.CAP = cap;
+  const int h2 = g.Pe / 2;
+  g.KS = g.C * h2 * h2;
+  for (int t = 0; t < g.KS; ++t) {
+    const int c = t / (h2 * h2);
+    const int rem = t - c * h2 * h2;
+    const int l2 = rem / h2;
+    const int m2 = rem - l2 * h2;
+    g.step_off[t] = c * g.PLANE + 2 * l2 * g.RS + 2 * m2;
+    uint32_t mask = 0;
+    for (int gp = 0; gp < 4; ++gp) {
+      const int l = 2 * l2 + (gp >> 1);
+      const int m = 2 * m2 + (gp & 1);
+      if (l < g.P && m < g.P) mask |= 1u << gp;
+    }
+    g.step_mask[t] = mask;
+  }
+  const int nw = wy * wx;
+  const int strip_bytes = g.C * g.PLANE * 4;
+  const int norm_bytes = g.NH * g.NRS * 4;
+  const int buf_bytes = nw * 16 * cap * 8;
+  g.lds_strip_off = 0;
+  g.lds_norm_off = (strip_bytes + 15) & ~15;
+  g.lds_buf_off = (g.lds_norm_off + norm_bytes + 15) & ~15;
+  g.lds_bytes = g.lds_buf_off + buf_bytes;
+  g.pre_scale = 1.f;
+  g.post_scale = 1.f;
+}
+
+}  // namespace bmk
+
+using namespace bmk;
+
+extern "C" {
+
+const char* bm_status_str(bm_status s) {
+  switch (s) {
+    case BM_OK: return "BM_OK";
+    case BM_EINVAL: return "BM_EINVAL";
+    case BM_ENOMEM: return "BM_ENOMEM";
+    case BM_EDEVICE: return "BM_EDEVICE";
+    case BM_EAGAIN: return "BM_EAGAIN";
+    case BM_EBUSY: return "BM_EBUSY";
+    case BM_ENOTFOUND: return "BM_ENOTFOUND";
+    case BM_ECANCELED: return "BM_ECANCELED";
+    case BM_ENOTSUP: return "BM_ENOTSUP";
+  }
+  return "BM_UNKNOWN";
+}
+
+const char* bm_last_error(void) { return last_error(); }
+
+bm_status bm_plan(const bm_desc* desc, bm_plan_t* out) {
+  if (!out) return fail(BM_EINVAL, "out is NULL");
+  *out = nullptr;
+  bm_status st = validate_desc(desc);
+  if (st != BM_OK) return st;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  int max_lds = 0;
+  e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+  bm_plan_s* p = new (std::nothrow) bm_plan_s();
+  if (!p) return fail(BM_ENOMEM, "host allocation failed");
+  p->desc = *desc;
+  p->device = dev;
+  st = choose_config(*desc, max_lds, p);
+  if (st != BM_OK) {
+    delete p;
+    return st;
+  }
+  p->ws_bytes = plan_workspace_bytes(*p);
+  if (p->ws_bytes > 0) {
+    e = hipMalloc(&p->ws, p->ws_bytes);
+    if (e != hipSuccess) {
+      delete p;
+      (void)hipGetLastError();
+      return fail(BM_ENOMEM, "workspace hipMalloc(%lld): %s", (long long)p->ws_bytes,
+                  hipGetErrorString(e));
+    }
+  }
+  *out = p;
+  return BM_OK;
+}
+
+bm_status bm_plan_info(bm_plan_t plan, int64_t* n_ref, int64_t* workspace_bytes) {
+  if (!plan) return fail(BM_EINVAL, "plan is NULL");
+  if (n_ref) *n_ref = (int64_t)plan->geom.nry * plan->geom.nrx;
+  if (workspace_bytes) *workspace_bytes = plan->ws_bytes;
+  return BM_OK;
+}
+
+bm_status bm_plan_destroy(bm_plan_t plan) {
+  if (!plan) return fail(BM_EINVAL, "plan is NULL");
+  if (plan->ws) (void)hipFree(plan->ws);
+  delete plan;
+  return BM_OK;
+}
+
+bm_status bm_norms(bm_plan_t plan, const float* d_img, float* d_norm, void* stream) {
+  if (!plan) return fail(BM_EINVAL, "plan is NULL");
+  if (!d_img || !d_norm) return fail(BM_EINVAL, "NULL device pointer");
+  const XcGeom& g = plan->geom;
+  NormGeom ng{g.H, g.W, g.C, g.P, g.Hv, g.Wv};
+  hipError_t e = launch_norm(d_img, d_norm, ng, g.center, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "norm launch");
+  return BM_OK;
+}
+
+bm_status bm_match(bm_plan_t plan, const float* d_img, int32_t* d_idx, float* d_dist,
+                   void* d_workspace, void* stream) {
+  if (!plan) return fail(BM_EINVAL, "plan is NULL");
+  if (!d_img || !d_idx || !d_dist) return fail(BM_EINVAL, "NULL device pointer");
+  void* ws = d_workspace ? d_workspace : plan->ws;
+  hipStream_t s = (hipStream_t)stream;
+  return run_match(*plan, d_img, d_idx, d_dist, ws, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,43 @@
+// Internal definitions shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace bmk {
+
+// Largest contraction handled in registers: k-steps of 4 elements (fp32 matrix op) for
+// one reference patch.  C * ceil(P/2)^2 <= 64, i.e. C * Pe^2 <= 256 with Pe = P rounded up
+// to even.
+constexpr int kMaxSteps = 64;
+constexpr int kMaxK = 64;
+constexpr int kRefBlock = 4;      // a wave owns a 4 x 4 block of references
+constexpr int kTileN = 16;        // candidates per matrix tile (one row segment)
+
+// Geometry of one fused cross-term / distance / top-K launch.  All sizes in elements.
+struct XcGeom {
+  int H, W, C, P, Pe, s, r, K;
+  int Hv, Wv;           // valid patch positions per axis
+  int nry, nrx;         // reference grid
+  int WY, WX;           // wave grid inside a workgroup (each wave: 4 x 4 references)
+  int nwg_y, nwg_x, nwg_total;
+  int NT;               // 16-wide candidate tiles per candidate row (per wave, max)
+  int SH, SW, RS, PLANE;  // pixel strip in LDS: rows, cols, row stride, channel stride
+  int NH, NW, NRS;      // patch-norm strip in LDS: rows, cols, row stride
+  int CAP;              // candidate buffer entries per reference
+  int KS;               // real k-steps (the rest of the template's steps are zero-padded)
+  int lds_strip_off, lds_norm_off, lds_buf_off, lds_bytes;
+  // split forms: element scale applied before the split (power of two) and its inverse^2
+  float pre_scale, post_scale;
+  // k-step table: LDS offset of each step relative to a patch's top-left corner, and the
+  // mask of lane groups (bit g) whose element lies inside the P x P patch (odd P pads).
+  int step_off[kMaxSteps];
+  uint32_t step_mask[kMaxSteps];
+  // per-channel centring constants (zeros unless BM_FLAG_CENTER)
+  float center[8];
+};
+
+struct NormGeom {
+  int H, W, C, P, Hv, Wv;
+};
+
+}  // namespace bmk

@@ -1,0 +1,82 @@
+// Patch-norm box filter for gfx950.
+//
+// N[y][x] = sum_c sum_{l<P} sum_{m<P} (X_c[y+l][x+m] - center_c)^2, the entries of
+// h_X (.) h_X (Sec. III-B, the normalisation vector h_X; used by Lemma 2).
+//
+// One workgroup produces a 16 x 64 output tile.  It stages the (16+P-1) x (64+P-1) input
+// window of one channel in LDS with coalesced row loads, forms the horizontal P-tap sums of
+// squares, then the vertical P-tap sums, and accumulates over channels.  Sums are direct
+// (no prefix or summed-area tables, whose rounding grows with the image) and carried in
+// float64, so every output is the float32 rounding of the exact norm.  HBM-bound: each
+// input element is read once from HBM and each output written once.
+#include <hip/hip_runtime.h>
+#include "bm_internal.h"
+
+namespace bmk {
+
+constexpr int kNormTX = 64;
+constexpr int kNormTY = 16;
+constexpr int kMaxP = 16;
+
+__global__ void __launch_bounds__(256)
+norm_box_kernel(const float* __restrict__ img, float* __restrict__ out, NormGeom g,
+                float c0, float c1, float c2, float c3, float c4, float c5, float c6, float c7) {
+  __shared__ float tile[kNormTY + kMaxP - 1][kNormTX + kMaxP];
+  __shared__ double hs[kNormTY + kMaxP - 1][kNormTX];
+  const float centers[8] = {c0, c1, c2, c3, c4, c5, c6, c7};
+  const int tx = threadIdx.x & 63;
+  const int ty = threadIdx.x >> 6;  // 0..3
+  const int ox0 = blockIdx.x * kNormTX;
+  const int oy0 = blockIdx.y * kNormTY;
+  const int rows = kNormTY + g.P - 1;
+  const int cols = kNormTX + g.P - 1;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+
+  for (int c = 0; c < g.C; ++c) {
+    const float* plane = img + (size_t)c * g.H * g.W;
+    const float cc = centers[c];
+    for (int rr = ty; rr < rows; rr += 4) {
+      const int y = oy0 + rr;
+      for (int xx = tx; xx < cols; xx += 64) {
+        const int x = ox0 + xx;
+        float v = 0.f;
+        if (y < g.H && x < g.W) v = plane[(size_t)y * g.W + x] - cc;
+        tile[rr][xx] = v;
+      }
+    }
+    __syncthreads();
+    for (int rr = ty; rr < rows; rr += 4) {
+      double s = 0.0;
+      for (int m = 0; m < g.P; ++m) {
+        const double v = (double)tile[rr][tx + m];
+        s += v * v;
+      }
+      hs[rr][tx] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int row = ty * 4 + k;
+      double s = 0.0;
+      for (int l = 0; l < g.P; ++l) s += hs[row + l][tx];
+      acc[k] += s;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int oy = oy0 + ty * 4 + k;
+    const int ox = ox0 + tx;
+    if (oy < g.Hv && ox < g.Wv) out[(size_t)oy * g.Wv + ox] = (float)acc[k];
+  }
+}
+
+hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* center,
+                       hipStream_t stream) {
+  dim3 grid((g.Wv + kNormTX - 1) / kNormTX, (g.Hv + kNormTY - 1) / kNormTY);
+  hipLaunchKernelGGL(norm_box_kernel, grid, dim3(256), 0, stream, img, out, g, center[0],
+                     center[1], center[2], center[3], center[4], center[5], center[6], center[7]);
+  return hipGetLastError();
+}
+
+}  // namespace bmk

@@ -1,0 +1,27 @@
+// Batch and serving entry points (filled in by their own sources).
+#include "plan.h"
+
+using namespace bmk;
+
+extern "C" {
+
+bm_status bm_batch_workspace(int32_t, const bm_plan_t*, int64_t*) {
+  return fail(BM_ENOTSUP, "batch path not built");
+}
+bm_status bm_match_batch(int32_t, const bm_plan_t*, const float* const*, int32_t* const*,
+                         float* const*, void*, void*) {
+  return fail(BM_ENOTSUP, "batch path not built");
+}
+bm_status bm_server_create(const bm_server_cfg*, bm_server_t*) {
+  return fail(BM_ENOTSUP, "server not built");
+}
+bm_status bm_submit(bm_server_t, const bm_desc*, const float*, uint64_t*) {
+  return fail(BM_ENOTSUP, "server not built");
+}
+bm_status bm_poll(bm_server_t, uint64_t, int32_t*, float*, bm_request_stats*) {
+  return fail(BM_ENOTSUP, "server not built");
+}
+bm_status bm_cancel(bm_server_t, uint64_t) { return fail(BM_ENOTSUP, "server not built"); }
+bm_status bm_server_destroy(bm_server_t) { return fail(BM_ENOTSUP, "server not built"); }
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+"""Parity rules between the GPU path and the FP64 oracle (test infrastructure).
+
+Distance rule (float32 path): for every returned pair,
+    |d_gpu - d*| <= tol * max(d*, floor * (N*_i + N*_j))
+where d* is the oracle distance and N* the oracle patch norms; the floor scales with the
+operands of the cancellation N_i + N_j - 2C in Lemma 2 (exact zero distances are compared
+against that scale rather than against zero).
+
+Set rule: with t the oracle's K-th distance and tau = tol * max(t, floor*(N*_i + N*_jK)),
+the GPU set holds min(K, |Cand|) distinct in-window candidates, every member has
+d* <= t + tau, and every candidate with d* < t - tau is a member.  When the oracle's K-th
+and (K+1)-th distances differ by more than tau this forces the exact oracle set.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import bm_oracle as O
+
+
+class ParityReport:
+    def __init__(self):
+        self.rel = []
+        self.strict_mismatch = 0
+        self.tolerant_mismatch = 0
+        self.order_violations = 0
+        self.n_refs = 0
+        self.messages = []
+
+    def summary(self):
+        r = np.concatenate(self.rel) if self.rel else np.zeros(1)
+        return {"refs": self.n_refs, "rel_max": float(r.max()), "rel_p99": float(np.quantile(r, 0.99)),
+                "rel_median": float(np.median(r)), "strict_set_mismatch": self.strict_mismatch,
+                "tolerant_set_mismatch": self.tolerant_mismatch, "order_violations": self.order_violations}
+
+
+def check(x, P, s, Wn, K, gpu_idx, gpu_dist, refs=None, tol=1e-4, floor=1e-2, report=None):
+    """Check GPU rows (for reference numbers ``refs``, default all) against the oracle."""
+    x64 = np.asarray(x, dtype=np.float64)
+    if x64.ndim == 2:
+        x64 = x64[None]
+    C, H, W = x64.shape
+    Hv, Wv = H - P + 1, W - P + 1
+    N = O.patch_norms(x64, P)
+    rl = O.ref_list(H, W, P, s)
+    sel = np.arange(len(rl)) if refs is None else np.asarray(refs)
+    gpu_idx = np.asarray(gpu_idx)
+    gpu_dist = np.asarray(gpu_dist)
+    rep = report or ParityReport()
+    for row, i in enumerate(sel):
+        ry, rx = int(rl[i, 0]), int(rl[i, 1])
+        d, j = O.window_distances(x64, P, Wn, ry, rx)
+        ncand = d.size
+        oidx, odist = O.select_k(d, j, K)
+        lookup = dict(zip(j.tolist(), d.tolist()))
+        gi = gpu_idx[row]
+        gd = gpu_dist[row]
+        rep.n_refs += 1
+        kk = min(K, ncand)
+        # padding
+        if np.any(gi[kk:] != -1) or np.any(np.isfinite(gd[kk:])):
+            rep.tolerant_mismatch += 1
+            rep.messages.append(f"ref {i}: bad padding")
+            continue
+        members = gi[:kk].tolist()
+        if len(set(members)) != kk or any(m not in lookup for m in members):
+            rep.tolerant_mismatch += 1
+            rep.messages.append(f"ref {i}: non-candidate or duplicate indices {members}")
+            continue
+        dstar = np.array([lookup[m] for m in members])
+        ni = N[ry, rx]
+        nj = np.array([N[m // W, m % W] for m in members])
+        rel = np.abs(gd[:kk].astype(np.float64) - dstar) / np.maximum(dstar, floor * (ni + nj))
+        rep.rel.append(rel)
+        if np.any(rel > tol):
+            rep.tolerant_mismatch += 1
+            rep.messages.append(f"ref {i}: rel error {rel.max():.3e}")
+        # ascending order of the GPU's own keys
+        keys = list(zip(gd[:kk].tolist(), members))
+        if keys != sorted(keys):
+            rep.order_violations += 1
+        # set rule
+        t = odist[kk - 1]
+        jk = int(oidx[kk - 1])
+        tau = tol * max(t, floor * (ni + N[jk // W, jk % W]))
+        if set(members) != set(oidx[:kk].tolist()):
+            rep.strict_mismatch += 1
+            must = {int(a) for a, b in zip(j, d) if b < t - tau}
+            if np.any(dstar > t + tau) or not must.issubset(set(members)):
+                rep.tolerant_mismatch += 1
+                rep.messages.append(f"ref {i}: set rule violated")
+    return rep
+
+
+def check_exact(gpu_idx, gpu_dist, oidx, odist):
+    """Bit-exact comparison for integer-valued inputs where float32 arithmetic is exact."""
+    assert np.array_equal(np.asarray(gpu_idx), oidx)
+    assert np.array_equal(np.asarray(gpu_dist).astype(np.float64), odist)

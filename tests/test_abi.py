@@ -1,0 +1,78 @@
+"""C-ABI surface checks that need no GPU: exports, argument validation, error strings."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from tests.libutil import ROOT, ensure_built
+
+HEADER = os.path.join(ROOT, "include", "bm.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(bm_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["bm_plan", "bm_plan_info", "bm_match", "bm_match_batch", "bm_plan_destroy",
+              "bm_server_create", "bm_submit", "bm_poll", "bm_cancel", "bm_server_destroy",
+              "bm_status_str", "bm_last_error", "bm_norms", "bm_batch_workspace"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    bm = ensure_built()
+    h = C.CDLL(bm.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(h, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    bm = ensure_built()
+    assert bm.bm_status_str(0) == "BM_OK"
+    assert bm.bm_status_str(bm.BM_EINVAL) == "BM_EINVAL"
+    assert bm.bm_status_str(bm.BM_EBUSY) == "BM_EBUSY"
+    assert bm.bm_status_str(12345) == "BM_UNKNOWN"
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("height", 0, "height"), ("channels", 9, "channels"), ("patch", 0, "patch"),
+    ("patch", 17, "patch"), ("stride", 0, "stride"), ("window", 4, "odd"), ("window", 0, "odd"),
+    ("k", 0, "k must"), ("k", 65, "k must"), ("precision", 7, "precision"), ("flags", 8, "flag"),
+])
+def test_invalid_descriptors_rejected_on_host(field, value, needle):
+    bm = ensure_built()
+    d = bm.make_desc(64, 64, 1, 8, 3, 21, 16)
+    setattr(d, field, value)
+    with pytest.raises(bm.BMError) as ei:
+        bm.bm_plan(d)
+    assert ei.value.status == bm.BM_EINVAL
+    assert needle in str(ei.value)
+
+
+def test_patch_larger_than_image_rejected():
+    bm = ensure_built()
+    with pytest.raises(bm.BMError) as ei:
+        bm.bm_plan(bm.make_desc(5, 40, 1, 8, 1, 3, 4))
+    assert ei.value.status == bm.BM_EINVAL
+
+
+def test_unsupported_contraction_is_enotsup():
+    bm = ensure_built()
+    with pytest.raises(bm.BMError) as ei:
+        bm.bm_plan(bm.make_desc(64, 64, 8, 8, 1, 3, 4))  # 8 * 16 steps > 64
+    assert ei.value.status == bm.BM_ENOTSUP
+
+
+def test_null_arguments():
+    bm = ensure_built()
+    lib = bm.lib()
+    assert lib.bm_plan(None, None) == bm.BM_EINVAL
+    assert lib.bm_plan_info(None, None, None) == bm.BM_EINVAL
+    assert lib.bm_match(None, None, None, None, None, None) == bm.BM_EINVAL
+    assert lib.bm_plan_destroy(None) == bm.BM_EINVAL
+    assert "NULL" in bm.bm_last_error()
