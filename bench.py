@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Block-matching throughput on one MI355X: ref-patches/s and per-step latency.
+
+Workload: one 512x512 grayscale float32 image (Voronoi cells + noise sigma 50/255, seed 1),
+8x8 patches, reference stride 3, 39x39 search window, K = 16 -- 28,561 references and
+41,615,401 in-window pairs per step.  A step is the whole path on the resident image:
+the patch-norm box filter (bm_norms) followed by the fused cross-term / distance / top-K
+kernel (bm_cross_topk); the two calls together are exactly bm_match.
+
+Output: one JSON line.  `value` is ref-patches/s of the reported form over the timed
+region (inputs already in HBM); `roofline` covers the dominant kernel (the cross-term
+kernel), timed with HIP events on its own launch stream; `cpu_baseline` times the FP64
+oracle on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ref patches/s (top-16, 8x8 patch, 39x39 window) vs plain FP32; p50/p99 latency"
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "fp16x3": 2500.0}  # dense matrix-core peaks
+DTYPE = {"fp32": "f32", "bf16x3": "bf16x3->f32", "fp16x3": "f16x3->f32"}
+KERNEL_SOURCES = {
+    "fp32": ["xcorr_f32.hip", "topk.h", "bm_internal.h"],
+    "bf16x3": ["xcorr_split.hip", "topk.h", "bm_internal.h"],
+    "fp16x3": ["xcorr_split.hip", "topk.h", "bm_internal.h"],
+}
+
+
+def source_hash(prec: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[prec]:
+        p = os.path.join(ROOT, "paper_2006_13714_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def pair_count(H, W, P, s, Wn):
+    """In-window (reference, candidate) pairs: the clipped window is separable per axis."""
+    r = Wn // 2
+
+    def axis(n):
+        nv = n - P + 1
+        return sum(min(nv - 1, c + r) - max(0, c - r) + 1 for c in range(0, nv, s))
+
+    return axis(H) * axis(W)
+
+
+def traffic_from_profile(prec: str, workload: str):
+    """HBM bytes per launch from the committed counter summary, if it matches this source."""
+    path = os.path.join(ROOT, "profiles", f"xcorr_{prec}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != source_hash(prec):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(img, sh, budget_s: float):
+    """FP64 oracle on every second reference (bounded by budget_s), refs/s on one core."""
+    import numpy as np
+    from oracle import bm_oracle as O
+
+    n_ref = sh.n_ref
+    sample = np.arange(0, n_ref, 2)
+    done = 0
+    t0 = time.perf_counter()
+    for start in range(0, len(sample), 256):
+        O.bm(img, sh.patch, sh.stride, sh.window, sh.k, refs=sample[start:start + 256])
+        done += len(sample[start:start + 256])
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "ref-patches/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of {n_ref} references (every 2nd, row-major) of the same "
+                      f"512x512 image, numpy float64 brute force, {dt:.1f} s",
+            "host_threads_available": len(os.sched_getaffinity(0))}
+
+
+def run_form(bm, torch, img_t, sh, prec, steps, warmup):
+    desc = bm.make_desc(sh.height, sh.width, sh.channels, sh.patch, sh.stride, sh.window,
+                        sh.k, prec)
+    plan = bm.bm_plan(desc)
+    dev = img_t.device
+    nrm = torch.empty(((sh.height - sh.patch + 1) * (sh.width - sh.patch + 1),),
+                      dtype=torch.float32, device=dev)
+    idx = torch.empty((plan.n_ref, sh.k), dtype=torch.int32, device=dev)
+    dist = torch.empty((plan.n_ref, sh.k), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        bm.bm_norms(plan, img_t, nrm, stream)
+        bm.bm_cross_topk(plan, img_t, nrm, idx, dist, stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record(stream)
+        bm.bm_norms(plan, img_t, nrm, stream)
+        ev[i][1].record(stream)
+        bm.bm_cross_topk(plan, img_t, nrm, idx, dist, stream)
+        ev[i][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    norm_ms = [a.elapsed_time(b) for a, b, _ in ev]
+    xc_ms = [b.elapsed_time(c) for _, b, c in ev]
+    step_ms = [a.elapsed_time(c) for a, _, c in ev]
+    return plan, wall, norm_ms, xc_ms, step_ms, (idx, dist)
+
+
+def quantile(v, q):
+    s = sorted(v)
+    k = min(len(s) - 1, max(0, int(round(q * (len(s) - 1)))))
+    return s[k]
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp32", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of oracle work for the CPU baseline (0 disables it)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 64 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
+              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2006_13714_amd import bm, synth
+
+    if not os.path.exists(bm.LIB_PATH):
+        from paper_2006_13714_amd import build_lib
+        build_lib.build()
+
+    w = synth.gray512()
+    sh = w.shape
+    img_t = torch.from_numpy(w.image).to("cuda:0")
+
+    if args.calib_copy:
+        src = torch.ones(16 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    results = {}
+    forms = ["fp32"] if args.precision == "fp32" else ["fp32", args.precision]
+    for prec in forms:
+        results[prec] = run_form(bm, torch, img_t, sh, prec, args.steps, args.warmup)
+
+    prec = args.precision
+    plan, wall, norm_ms, xc_ms, step_ms, _ = results[prec]
+    n_ref = plan.n_ref
+    value = n_ref * args.steps / wall
+    pairs = pair_count(sh.height, sh.width, sh.patch, sh.stride, sh.window)
+    flops = 2.0 * sh.patch * sh.patch * sh.channels * pairs
+    xc_avg_s = sum(xc_ms) / len(xc_ms) / 1e3
+    achieved = flops / xc_avg_s / 1e12
+    peak = PEAK_TFLOPS[prec]
+    traffic = traffic_from_profile(prec, w.name)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "ref-patches/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[prec],
+        "data": "synthetic",
+        "config": {"workload": w.name, "height": sh.height, "width": sh.width,
+                   "channels": sh.channels, "patch": sh.patch, "stride": sh.stride,
+                   "window": sh.window, "k": sh.k, "precision": prec, "n_ref": n_ref,
+                   "pairs": pairs, "seed": w.seed},
+        "latency_ms": {"p50": quantile(step_ms, 0.5), "p99": quantile(step_ms, 0.99),
+                       "norm_avg": sum(norm_ms) / len(norm_ms),
+                       "cross_topk_avg": xc_avg_s * 1e3},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": f"xcorr_topk ({prec})",
+                     "algorithmic_flops_per_launch": flops},
+    }
+    if prec != "fp32":
+        p32, wall32, *_ = results["fp32"]
+        v32 = p32.n_ref * args.steps / wall32
+        out["plain_fp32"] = {"value": v32, "speedup": value / v32}
+    if args.cpu_budget > 0:
+        out["cpu_baseline"] = cpu_baseline(w.image, sh, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

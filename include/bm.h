@@ -95,6 +95,13 @@ bm_status bm_match(bm_plan_t plan, const float* d_img, int32_t* d_idx, float* d_
  * (H-P+1)*(W-P+1) floats, row-major.  Asynchronous on `stream`. */
 bm_status bm_norms(bm_plan_t plan, const float* d_img, float* d_norm, void* stream);
 
+/* Second step of bm_match on its own: the fused cross-term / distance / top-K kernel,
+ * given the norm map that bm_norms wrote for the same image (d_norm, (H-P+1)*(W-P+1)
+ * floats).  Together the two calls compute exactly what bm_match computes.
+ * Asynchronous on `stream`. */
+bm_status bm_cross_topk(bm_plan_t plan, const float* d_img, const float* d_norm,
+                        int32_t* d_idx, float* d_dist, void* stream);
+
 /* Many images of uneven shapes in one persistent launch (plus one norm launch).  Entry b
  * uses plans[b], d_imgs[b], d_idx[b], d_dist[b].  d_workspace must hold
  * bm_batch_workspace() bytes or be NULL (then the library allocates and frees it inside

@@ -62,6 +62,8 @@ _SIGS = {
     "bm_plan_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "bm_match": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bm_norms": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bm_cross_topk": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]),
     "bm_match_batch": (C.c_int32, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                    C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p,
                                    C.c_void_p]),
@@ -178,6 +180,11 @@ def bm_match(plan: Plan, img, idx, dist, workspace=None, stream=None):
 
 def bm_norms(plan: Plan, img, norm, stream=None):
     _check(lib().bm_norms(plan.handle, _ptr(img), _ptr(norm), _stream(stream)), "bm_norms")
+
+
+def bm_cross_topk(plan: Plan, img, norm, idx, dist, stream=None):
+    _check(lib().bm_cross_topk(plan.handle, _ptr(img), _ptr(norm), _ptr(idx), _ptr(dist),
+                               _stream(stream)), "bm_cross_topk")
 
 
 def bm_batch_workspace(plans) -> int:

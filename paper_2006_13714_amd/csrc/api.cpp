@@ -13,9 +13,6 @@
 
 namespace bmk {
 
-hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* center,
-                       hipStream_t stream);
-
 static thread_local std::string g_err;
 
 bm_status fail(bm_status s, const char* fmt, ...) {
@@ -56,8 +53,11 @@ bm_status validate_desc(const bm_desc* d) {
   return BM_OK;
 }
 
-// Fill the launch geometry for a wave grid (wy x wx) and buffer capacity `cap`.
-void fill_geom(const bm_desc& d, int wy, int wx, int cap, XcGeom& g) {
+// Fill the launch geometry.  Generic kernel: a workgroup of wy x wx waves, one 4 x 4
+// reference block per wave, channel-plane strip.  Specialised kernel (`fast`): one
+// reference block per workgroup shared by wy waves (wx unused), channel-interleaved strip
+// rows of kFastRS floats.  `cap`: candidate buffer entries per reference.
+void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) {
   memset(&g, 0, sizeof(g));
   g.H = d.height;
   g.W = d.width;
@@ -71,19 +71,27 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, XcGeom& g) {
   g.Wv = d.width - d.patch + 1;
   g.nry = (d.height - d.patch) / d.stride + 1;
   g.nrx = (d.width - d.patch) / d.stride + 1;
+  g.fast = fast ? 1 : 0;
+  g.p1_step = 2;
+  if (fast) {
+    wx = 1;
+    g.WS = wy;
+  }
   g.WY = wy;
   g.WX = wx;
-  g.nwg_y = (g.nry + kRefBlock * wy - 1) / (kRefBlock * wy);
-  g.nwg_x = (g.nrx + kRefBlock * wx - 1) / (kRefBlock * wx);
+  const int rows_per_wg = fast ? kRefBlock : kRefBlock * wy;
+  const int cols_per_wg = fast ? kRefBlock : kRefBlock * wx;
+  g.nwg_y = (g.nry + rows_per_wg - 1) / rows_per_wg;
+  g.nwg_x = (g.nrx + cols_per_wg - 1) / cols_per_wg;
   g.nwg_total = g.nwg_y * g.nwg_x;
   const int span = 3 * g.s + 2 * g.r + 1;  // candidate positions across a 4-reference block
   g.NT = (span + kTileN - 1) / kTileN;
-  g.NH = 4 * g.s * (wy - 1) + span;
-  g.NW = 4 * g.s * (wx - 1) + kTileN * g.NT;
+  g.NH = (fast ? 0 : 4 * g.s * (wy - 1)) + span;
+  g.NW = (fast ? 0 : 4 * g.s * (wx - 1)) + kTileN * g.NT;
   g.NRS = g.NW;
   g.SH = g.NH + g.Pe - 1;
   g.SW = g.NW + g.Pe - 1;
-  g.RS = g.SW;
+  g.RS = fast ? kFastRS : g.SW;
   g.PLANE = g.SH * g.RS;
   g.CAP = cap;
   const int h2 = g.Pe / 2;
@@ -103,9 +111,16 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, XcGeom& g) {
     g.step_mask[t] = mask;
   }
   const int nw = wy * wx;
-  const int strip_bytes = g.C * g.PLANE * 4;
+  const int strip_bytes = g.C * g.SH * g.RS * 4;
   const int norm_bytes = g.NH * g.NRS * 4;
-  const int buf_bytes = nw * 16 * cap * 8;
+  int buf_bytes = nw * 16 * cap * 8;
+  if (fast) {
+    const int kr = d.k <= 16 ? 1 : 2;
+    const int tl_bytes = nw * 4 * (2 * kr) * 64 * 4;   // bounding-list exchange
+    const int list_bytes = (nw - 1) * 4 * kr * 64 * 8;  // final-list exchange
+    buf_bytes = buf_bytes > tl_bytes ? buf_bytes : tl_bytes;
+    buf_bytes = buf_bytes > list_bytes ? buf_bytes : list_bytes;
+  }
   g.lds_strip_off = 0;
   g.lds_norm_off = (strip_bytes + 15) & ~15;
   g.lds_buf_off = (g.lds_norm_off + norm_bytes + 15) & ~15;
@@ -188,11 +203,14 @@ bm_status bm_plan_destroy(bm_plan_t plan) {
 bm_status bm_norms(bm_plan_t plan, const float* d_img, float* d_norm, void* stream) {
   if (!plan) return fail(BM_EINVAL, "plan is NULL");
   if (!d_img || !d_norm) return fail(BM_EINVAL, "NULL device pointer");
-  const XcGeom& g = plan->geom;
-  NormGeom ng{g.H, g.W, g.C, g.P, g.Hv, g.Wv};
-  hipError_t e = launch_norm(d_img, d_norm, ng, g.center, (hipStream_t)stream);
-  if (e != hipSuccess) return hip_fail(e, "norm launch");
-  return BM_OK;
+  return run_norms(*plan, d_img, d_norm, (hipStream_t)stream);
+}
+
+bm_status bm_cross_topk(bm_plan_t plan, const float* d_img, const float* d_norm,
+                        int32_t* d_idx, float* d_dist, void* stream) {
+  if (!plan) return fail(BM_EINVAL, "plan is NULL");
+  if (!d_img || !d_norm || !d_idx || !d_dist) return fail(BM_EINVAL, "NULL device pointer");
+  return run_cross_topk(*plan, d_img, d_norm, d_idx, d_dist, (hipStream_t)stream);
 }
 
 bm_status bm_match(bm_plan_t plan, const float* d_img, int32_t* d_idx, float* d_dist,

@@ -12,6 +12,7 @@ constexpr int kMaxSteps = 64;
 constexpr int kMaxK = 64;
 constexpr int kRefBlock = 4;      // a wave owns a 4 x 4 block of references
 constexpr int kTileN = 16;        // candidates per matrix tile (one row segment)
+constexpr int kFastRS = 80;       // LDS row stride (floats) of the specialised kernels
 
 // Geometry of one fused cross-term / distance / top-K launch.  All sizes in elements.
 struct XcGeom {
@@ -19,6 +20,10 @@ struct XcGeom {
   int Hv, Wv;           // valid patch positions per axis
   int nry, nrx;         // reference grid
   int WY, WX;           // wave grid inside a workgroup (each wave: 4 x 4 references)
+  int fast;             // 1: specialised kernel (one reference block per workgroup,
+                        //    channel-interleaved strip rows with row stride kFastRS)
+  int WS;               // specialised kernel: waves sharing one reference block
+  int p1_step;          // specialised kernel: bounding sweep visits every p1_step-th row
   int nwg_y, nwg_x, nwg_total;
   int NT;               // 16-wide candidate tiles per candidate row (per wave, max)
   int SH, SW, RS, PLANE;  // pixel strip in LDS: rows, cols, row stride, channel stride

@@ -10,7 +10,7 @@ struct bm_plan_s {
   bm_desc desc;
   int device = 0;
   bmk::XcGeom geom;
-  int ks_bucket = 0;    // compiled step count of the chosen kernel
+  int ks_bucket = 0;    // compiled step count of the generic kernel
   int kr = 1;           // list registers per reference (K <= 16 * kr)
   void* ws = nullptr;   // plan-owned workspace (norm map, split planes)
   int64_t ws_bytes = 0;
@@ -23,16 +23,20 @@ bm_status fail(bm_status s, const char* fmt, ...);
 bm_status hip_fail(hipError_t e, const char* what);
 const char* last_error();
 bm_status validate_desc(const bm_desc* d);
-void fill_geom(const bm_desc& d, int wy, int wx, int cap, XcGeom& g);
+void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g);
 
 // Tile configuration: wave grid per workgroup and candidate-buffer capacity.
 struct TileCfg {
   int wy, wx, cap;
+  bool fast;  // specialised kernel (C <= 4, patch <= 8, K <= 32, strip fits kFastRS)
 };
 
 bm_status choose_config(const bm_desc& d, int max_lds, bm_plan_s* p);
 bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_s* p);
 int64_t plan_workspace_bytes(const bm_plan_s& p);
+bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, hipStream_t s);
+bm_status run_cross_topk(const bm_plan_s& p, const float* d_img, const float* d_norm,
+                         int32_t* d_idx, float* d_dist, hipStream_t s);
 bm_status run_match(const bm_plan_s& p, const float* d_img, int32_t* d_idx, float* d_dist,
                     void* ws, hipStream_t s);
 

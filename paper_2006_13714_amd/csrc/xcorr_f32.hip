@@ -16,12 +16,15 @@
 //    laid out as 2 x 2 pixel blocks.  The references' patches stay in registers (operand A);
 //    candidate patches are read from the LDS strip with per-step offsets (operand B).  The
 //    overlapping candidates need no im2col: adjacent lanes read adjacent pixels.
-//  * Epilogue per tile: each lane holds 4 references x 1 candidate.  It assembles d in
-//    float32, applies the window mask, and compares with the reference's current K-th
-//    distance; survivors go to a per-reference LDS buffer via ballot/popcount compaction.
-//    Full buffers are merged into the per-reference sorted lists by the wavefront-shuffle
-//    bitonic networks of topk.h.  Candidates are visited in increasing j for every
-//    reference, so a strict "d < K-th distance" test is exact for the (d, j) order.
+//  * Software pipeline: operand B is double-buffered in registers; the LDS reads of the next
+//    tile are issued before the matrix-op chain of the current one.
+//  * Epilogue: each lane holds 4 references x 1 candidate and assembles d in float32 with
+//    the window mask.  Selection takes two sweeps with bit-identical arithmetic.  Sweep 1
+//    keeps, per lane, a branch-free min/max list of its smallest distances; the K-th
+//    smallest over the 16 lanes of a reference bounds that reference's K-th distance from
+//    above.  Sweep 2 appends only candidates under the bound (about K per reference) to a
+//    per-reference LDS buffer via ballot/popcount compaction, and the wavefront-shuffle
+//    bitonic networks of topk.h merge them into the sorted (d, j) lists.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -48,7 +51,7 @@ xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nwaves = blockDim.x >> 6;
 
   const int wg = xcd_remap(blockIdx.x, g.nwg_total);
@@ -65,23 +68,23 @@ xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
     const int c = row / g.SH;
     const int y = row - c * g.SH;
     const int iy = SY0 + y;
-    const bool yok = iy >= 0 && iy < g.H;
+    const bool yok = (iy >= 0) & (iy < g.H);
     const float cc = g.center[c];
     const float* src = img + ((size_t)c * g.H + (yok ? iy : 0)) * g.W;
     float* dst = strip + c * g.PLANE + y * g.RS;
     for (int x = lane; x < g.SW; x += 64) {
       const int ix = SX0 + x;
-      dst[x] = (yok && ix >= 0 && ix < g.W) ? src[ix] - cc : 0.f;
+      dst[x] = (yok & (ix >= 0) & (ix < g.W)) ? src[ix] - cc : 0.f;
     }
   }
   for (int y = wave; y < g.NH; y += nwaves) {
     const int qy = SY0 + y;
-    const bool yok = qy >= 0 && qy < g.Hv;
+    const bool yok = (qy >= 0) & (qy < g.Hv);
     const float* src = nrm + (size_t)(yok ? qy : 0) * g.Wv;
     float* dst = nstrip + y * g.NRS;
     for (int x = lane; x < g.NW; x += 64) {
       const int qx = SX0 + x;
-      dst[x] = (yok && qx >= 0 && qx < g.Wv) ? src[qx] : INFINITY;
+      dst[x] = (yok & (qx >= 0) & (qx < g.Wv)) ? src[qx] : INFINITY;
     }
   }
   __syncthreads();  // the only barrier: waves are independent from here on
@@ -119,7 +122,7 @@ xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
   int Lj[4][KR];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const bool ok = gp <= a_max && v <= b_max;
+    const bool ok = (gp <= a_max) & (v <= b_max);
     nr[v] = nstrip[(ryw + g.s * gp - SY0) * g.NRS + (rxw + g.s * v - SX0)];
     th[v] = ok ? INFINITY : -INFINITY;  // -inf: a padding reference admits nothing
     cnt[v] = 0;
@@ -131,16 +134,28 @@ xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
   }
   Entry* buf = buf_all + (size_t)wave * 16 * g.CAP;
 
-  const int qy_lo = max(0, ryw - g.r);
-  const int qy_hi = min(g.Hv - 1, ryw + g.s * a_max + g.r);
-  const int xs = rxw - g.r;  // first tile start (unclipped)
-  const int nt = (g.s * b_max + 2 * g.r + 1 + kTileN - 1) / kTileN;
+  // scalars the inner loops use (kept out of the kernel-argument struct so that nothing
+  // takes its address)
+  const int s = g.s, r = g.r, CAP = g.CAP, K = g.K, W = g.W, NRS = g.NRS, RS = g.RS;
+  constexpr int TL = 2 * KR;  // per-lane list length of the bounding pass
+  const int qy_lo = max(0, ryw - r);
+  const int qy_hi = min(g.Hv - 1, ryw + s * a_max + r);
+  const int xs = rxw - r;  // first tile start (unclipped)
+  const int nt = (s * b_max + 2 * r + 1 + kTileN - 1) / kTileN;
   const int tx_lo = xs < -(kTileN - 1) ? (-xs) / kTileN : 0;
   const int tx_hi = min(nt - 1, (g.Wv - 1 - xs) / kTileN);
+  const int n_tx = tx_hi - tx_lo + 1;
+  const int n_tiles = (qy_hi - qy_lo + 1) * n_tx;
   const unsigned long long grp_bits = 0xFFFFull << (16 * gp);
   const unsigned long long below = (1ull << lane) - 1ull;
+  const int lim = CAP - 16;
+  int soff[KS];
+#pragma unroll
+  for (int t = 0; t < KS; ++t) soff[t] = g.step_off[t];
+  const int bcol0 = (xs - SX0) + p16 + lane_off;  // operand B: lane offset inside a row
+  const float* nbase = nstrip + (xs - SX0) + p16;
 
-  auto flush = [&]() {
+  auto flush = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       for (int ch = 0; __any(ch * 16 < cnt[v]); ++ch) {
@@ -148,69 +163,177 @@ xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
         float cd = INFINITY;
         int cj = kNoIndex;
         if (e < cnt[v]) {
-          const Entry x = buf[(4 * gp + v) * g.CAP + e];
+          const Entry x = buf[(4 * gp + v) * CAP + e];
           cd = x.d;
           cj = x.j;
         }
         merge_batch<KR>(Ld[v], Lj[v], cd, cj, p16);
       }
       cnt[v] = 0;
-      const float kth = kth_distance<KR>(Ld[v], g.K);
-      th[v] = (th[v] == -INFINITY) ? -INFINITY : kth;
+      // never loosen: a list that is not yet full has K-th distance +inf (padding
+      // references keep -inf)
+      th[v] = fminf(th[v], kth_distance<KR>(Ld[v], K));
     }
   };
 
-  for (int qy = qy_lo; qy <= qy_hi; ++qy) {
-    const bool yin = abs(qy - ryw - g.s * gp) <= g.r;
-    const int srow = (qy - SY0) * g.RS;
-    const int nrow = (qy - SY0) * g.NRS;
-    for (int tx = tx_lo; tx <= tx_hi; ++tx) {
-      const int qx0 = xs + kTileN * tx;
-      const int bbase = srow + (qx0 - SX0) + p16 + lane_off;
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
+  // Pass-2 epilogue, split into a branch-free part (distances, window mask, admission test)
+  // that is interleaved with the next tile's matrix ops, and a commit part (ballot,
+  // compaction into the buffers, merges) that branches.
+  struct Admit {
+    float d[4];
+    bool pass[4];
+  };
+  auto admit = [&](const f4& acc, int qy, int tx) __attribute__((always_inline)) {
+    Admit a;
+    const float nc = nbase[(qy - SY0) * NRS + kTileN * tx];  // +inf off the valid range
+    const int xrel = xs + kTileN * tx + p16 - rxw;
+    const bool yin = abs(qy - ryw - s * gp) <= r;
 #pragma unroll
-      for (int t = 0; t < KS; ++t)
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[t], strip[bbase + g.step_off[t]], acc, 0, 0, 0);
-
-      const int qx = qx0 + p16;
-      const float nc = nstrip[nrow + (qx - SX0)];  // +inf outside the valid positions
-      const int jg = qy * g.W + qx;
-      const int xrel = qx - rxw;
-      bool added = false;
+    for (int v = 0; v < 4; ++v) {
+      a.d[v] = fmaf(-2.f, acc[v], nr[v] + nc);
+      a.pass[v] = yin & (abs(xrel - s * v) <= r) & (a.d[v] < th[v]);
+    }
+    return a;
+  };
+  auto commit = [&](const Admit& a, int qy, int tx) __attribute__((always_inline)) {
+    if (__any(a.pass[0] | a.pass[1] | a.pass[2] | a.pass[3])) {
+      const int jg = qy * W + xs + kTileN * tx + p16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const float d = nr[v] + nc - 2.f * acc[v];
-        const bool pass = yin && abs(xrel - g.s * v) <= g.r && d < th[v];
-        const unsigned long long m = __ballot(pass);
+        const unsigned long long m = __ballot(a.pass[v]);
         if (m) {
           const unsigned long long gm = m & grp_bits;
-          if (pass) {
+          if (a.pass[v]) {
             const int pos = cnt[v] + __popcll(gm & below);
-            buf[(4 * gp + v) * g.CAP + pos] = Entry{d, jg};
+            buf[(4 * gp + v) * CAP + pos] = Entry{a.d[v], jg};
           }
           cnt[v] += __popcll(gm);
-          added = true;
         }
       }
-      if (added) {
-        const int lim = g.CAP - 16;
-        if (__any(cnt[0] > lim || cnt[1] > lim || cnt[2] > lim || cnt[3] > lim)) flush();
-      }
+      if (__any((cnt[0] > lim) | (cnt[1] > lim) | (cnt[2] > lim) | (cnt[3] > lim))) flush();
     }
+  };
+
+  // One sweep over this wave's candidate tiles, software-pipelined: while the matrix ops
+  // of tile it run, the wave computes the branch-free epilogue of tile it-1 and issues the
+  // LDS reads of tile it+1 (the scheduling groups interleave one matrix op, a few vector
+  // ops and one LDS read).  The last iteration runs the chain on a clamped (in-bounds)
+  // repeat of the final tile whose result is discarded.
+  auto sweep = [&](auto&& arith, auto&& post) __attribute__((always_inline)) {
+    if (n_tiles <= 0) return;
+    int qy = qy_lo, tx = tx_lo;
+    auto tile_base = [&](int y, int x) __attribute__((always_inline)) {
+      return (min(y, qy_hi) - SY0) * RS + bcol0 + kTileN * x;
+    };
+    float b[KS];
+    f4 acc_prev = {0.f, 0.f, 0.f, 0.f};
+    {
+      const int bb = tile_base(qy, tx);
+#pragma unroll
+      for (int t = 0; t < KS; ++t) b[t] = strip[bb + soff[t]];
+#pragma unroll
+      for (int t = 0; t < KS; ++t)
+        acc_prev = __builtin_amdgcn_mfma_f32_16x16x4f32(A[t], b[t], acc_prev, 0, 0, 0);
+    }
+    int pqy = qy, ptx = tx;
+    auto advance = [&]() __attribute__((always_inline)) {
+      if (++tx > tx_hi) {
+        tx = tx_lo;
+        ++qy;
+      }
+    };
+    advance();
+    {
+      const int bb = tile_base(qy, tx);
+#pragma unroll
+      for (int t = 0; t < KS; ++t) b[t] = strip[bb + soff[t]];
+    }
+    // one pipeline step: matrix ops of the tile whose operands are in `cur`, the epilogue
+    // arithmetic of the previous tile, and the LDS reads of the next tile into `nxt`
+    auto step = [&](float (&cur)[KS], float (&nxt)[KS]) __attribute__((always_inline)) {
+      __builtin_amdgcn_sched_barrier(0);  // keep each step its own scheduling region
+      const int cqy = qy, ctx = tx;
+      advance();
+      const int nb = tile_base(qy, tx);
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < KS; ++t) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[t], cur[t], acc, 0, 0, 0);
+        nxt[t] = strip[nb + soff[t]];
+      }
+      auto res = arith(acc_prev, pqy, ptx);
+#pragma unroll
+      for (int t = 0; t < KS; ++t) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix op
+        __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // up to three vector ops
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      post(res, pqy, ptx);
+      acc_prev = acc;
+      pqy = cqy;
+      ptx = ctx;
+    };
+    // unrolled by two so the operand buffers swap roles without register copies
+    float b2[KS];
+    int it = 1;
+    for (; it + 1 <= n_tiles; it += 2) {
+      step(b, b2);
+      step(b2, b);
+    }
+    if (it <= n_tiles) step(b, b2);
+  };
+
+  // ---- pass 1: bound the K-th distance of every reference.  Each lane keeps the TL
+  // smallest in-window distances it sees (distances only); those 16*TL values belong to
+  // distinct candidates, so the K-th smallest of them is >= the true K-th distance.
+  float tl[4][TL];
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int i = 0; i < TL; ++i) tl[v][i] = INFINITY;
+  sweep(
+      [&](const f4& acc, int qy, int tx) __attribute__((always_inline)) {
+        const float nc = nbase[(qy - SY0) * NRS + kTileN * tx];
+        const int xrel = xs + kTileN * tx + p16 - rxw;
+        const bool yin = abs(qy - ryw - s * gp) <= r;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float d = fmaf(-2.f, acc[v], nr[v] + nc);
+          lane_insert<TL>(tl[v], (yin & (abs(xrel - s * v) <= r)) ? d : INFINITY);
+        }
+        return 0;
+      },
+      [&](int, int, int) __attribute__((always_inline)) {});
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    float L[KR];
+#pragma unroll
+    for (int q = 0; q < KR; ++q) L[q] = INFINITY;
+#pragma unroll
+    for (int i = 0; i < TL; ++i) merge_batch_d<KR>(L, tl[v][i], p16);
+    const float bound = kth_distance<KR>(L, K);
+    // strict "<" against the next float up admits exactly the candidates with d <= bound
+    th[v] = (th[v] == -INFINITY) ? -INFINITY : next_up(bound);
   }
+
+  // ---- pass 2: identical distances; candidates with d <= bound go to the buffers.  A
+  // merge (flush) lowers the threshold to the list's K-th distance; from then on every
+  // listed candidate precedes the rest in j, so the strict test stays exact.
+  sweep(admit, commit);
   flush();
 
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    if (gp <= a_max && v <= b_max) {
+    if ((gp <= a_max) & (v <= b_max)) {
       const size_t ref = (size_t)(RYw + gp) * g.nrx + (RXw + v);
 #pragma unroll
       for (int q = 0; q < KR; ++q) {
         const int e = 16 * q + p16;
-        if (e < g.K) {
+        if (e < K) {
           const bool none = Lj[v][q] == kNoIndex;
-          out_idx[ref * g.K + e] = none ? -1 : Lj[v][q];
-          out_dist[ref * g.K + e] = none ? INFINITY : fmaxf(Ld[v][q], 0.f);
+          out_idx[ref * K + e] = none ? -1 : Lj[v][q];
+          out_dist[ref * K + e] = none ? INFINITY : fmaxf(Ld[v][q], 0.f);
         }
       }
     }
@@ -256,13 +379,18 @@ XcKernel f32_kernel(int ks_bucket, int kr) {
   return nullptr;
 }
 
+// Allow the kernel the dynamic LDS of its tile (done once, at plan time).
+hipError_t prepare_xcorr_f32(int ks_bucket, int kr, int lds_bytes) {
+  XcKernel k = f32_kernel(ks_bucket, kr);
+  if (!k) return hipErrorInvalidValue;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+}
+
 hipError_t launch_xcorr_f32(int ks_bucket, int kr, const float* img, const float* nrm, int* idx,
                             float* dist, const XcGeom& g, hipStream_t stream) {
   XcKernel k = f32_kernel(ks_bucket, kr);
   if (!k) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, g.lds_bytes);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(g.nwg_total), dim3(64 * g.WY * g.WX), g.lds_bytes, stream, img, nrm,
                      idx, dist, g);
   return hipGetLastError();
