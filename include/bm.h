@@ -113,6 +113,22 @@ bm_status bm_batch_workspace(int32_t n, const bm_plan_t* plans, int64_t* bytes);
 
 bm_status bm_plan_destroy(bm_plan_t plan);
 
+/* ---- autotuning ------------------------------------------------------------------- */
+/* Time every kernel configuration that can run desc's shape class (waves per reference
+ * block or wave grid, bounding-sweep row step, candidate-buffer capacity) on the current
+ * device, `reps` launches each, on d_img (C*H*W device floats) or, if d_img is NULL, on a
+ * built-in structured test image.  The fastest is remembered for the shape class (channels,
+ * patch, stride, window, K/16, precision, coarse grid size) and used by later bm_plan calls
+ * in this process; with the environment variable BM_TUNE_CACHE naming a file it is also
+ * appended there and read back by later processes.  out_cfg (may be NULL) receives the
+ * configuration string.  Synchronous.  Errors: BM_EINVAL, BM_ENOMEM, BM_EDEVICE. */
+bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, char* out_cfg,
+                      int32_t out_len);
+
+/* Configuration string of a plan and where it came from (0 built-in rule, 1 autotuner
+ * table, 2 the BM_CFG environment override used for tuning experiments). */
+bm_status bm_plan_config(bm_plan_t plan, char* out_cfg, int32_t out_len, int32_t* source);
+
 /* ---- serving ---------------------------------------------------------------------- */
 typedef struct bm_server_s* bm_server_t;
 

@@ -75,6 +75,8 @@ _SIGS = {
                             C.POINTER(bm_request_stats)]),
     "bm_cancel": (C.c_int32, [C.c_void_p, C.c_uint64]),
     "bm_server_destroy": (C.c_int32, [C.c_void_p]),
+    "bm_autotune": (C.c_int32, [C.POINTER(bm_desc), C.c_void_p, C.c_int32, C.c_char_p, C.c_int32]),
+    "bm_plan_config": (C.c_int32, [C.c_void_p, C.c_char_p, C.c_int32, C.POINTER(C.c_int32)]),
     "bm_status_str": (C.c_char_p, [C.c_int32]),
     "bm_last_error": (C.c_char_p, []),
 }
@@ -205,6 +207,19 @@ def bm_match_batch(plans, imgs, idxs, dists, workspace=None, stream=None):
 
 def bm_plan_destroy(plan: Plan):
     plan.close()
+
+
+def bm_autotune(desc: bm_desc, img=None, reps: int = 10) -> str:
+    out = C.create_string_buffer(128)
+    _check(lib().bm_autotune(C.byref(desc), _ptr(img), reps, out, 128), "bm_autotune")
+    return out.value.decode()
+
+
+def bm_plan_config(plan: Plan):
+    out = C.create_string_buffer(128)
+    src = C.c_int32()
+    _check(lib().bm_plan_config(plan.handle, out, 128, C.byref(src)), "bm_plan_config")
+    return out.value.decode(), src.value
 
 
 def bm_server_create(hbm_budget_bytes: int, max_inflight: int = 64, max_queue: int = 4096) -> int:

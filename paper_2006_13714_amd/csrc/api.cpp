@@ -117,7 +117,7 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) 
   if (fast) {
     const int kr = d.k <= 16 ? 1 : 2;
     const int tl_bytes = nw * 4 * (2 * kr) * 64 * 4;   // bounding-list exchange
-    const int list_bytes = (nw - 1) * 4 * kr * 64 * 8;  // final-list exchange
+    const int list_bytes = nw * 4 * kr * 64 * 8;        // final-list exchange
     buf_bytes = buf_bytes > tl_bytes ? buf_bytes : tl_bytes;
     buf_bytes = buf_bytes > list_bytes ? buf_bytes : list_bytes;
   }

@@ -1,6 +1,9 @@
-// Plan configuration and the single-image launch sequence.
+// Plan configuration (built-in rule, autotuner table, explicit override) and the
+// single-image launch sequence.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "plan.h"
@@ -21,12 +24,47 @@ static int kr_for(int k) { return k <= 16 ? 1 : (k <= 32 ? 2 : 4); }
 
 static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
+bool parse_cfg(const char* text, TileCfg* out) {
+  if (!text) return false;
+  TileCfg c;
+  char kind[16] = {0};
+  int n = 0;
+  if (sscanf(text, "%15s%n", kind, &n) != 1) return false;
+  if (!strcmp(kind, "fast")) c.fast = true;
+  else if (!strcmp(kind, "generic")) c.fast = false;
+  else return false;
+  const char* p = text + n;
+  char key[16];
+  int val, m;
+  while (sscanf(p, " %15[a-z0-9]=%d%n", key, &val, &m) == 2) {
+    if (!strcmp(key, "ws") || !strcmp(key, "wy")) c.wy = val;
+    else if (!strcmp(key, "wx")) c.wx = val;
+    else if (!strcmp(key, "cap")) c.cap = val;
+    else if (!strcmp(key, "p1")) c.p1 = val;
+    else return false;
+    p += m;
+  }
+  while (*p == ' ') ++p;
+  if (*p) return false;
+  if (c.wy < 1 || c.wx < 1 || c.wy * c.wx > 4 || c.cap < 32 || c.cap > 256 || (c.cap & 15) ||
+      c.p1 < 1 || c.p1 > 8)
+    return false;
+  if (c.fast && c.wx != 1) return false;
+  *out = c;
+  return true;
+}
+
+void format_cfg(const TileCfg& c, char* out, int len) {
+  if (c.fast) snprintf(out, len, "fast ws=%d p1=%d cap=%d", c.wy, c.p1, c.cap);
+  else snprintf(out, len, "generic wy=%d wx=%d cap=%d", c.wy, c.wx, c.cap);
+}
+
 int64_t plan_workspace_bytes(const bm_plan_s& p) {
   const XcGeom& g = p.geom;
   return align256((int64_t)g.Hv * g.Wv * 4);
 }
 
-static bool fast_eligible(const bm_desc& d) {
+bool fast_eligible(const bm_desc& d) {
   const int h2 = (d.patch + 1) / 2;
   const int nt = (3 * d.stride + 2 * (d.window / 2) + 1 + kTileN - 1) / kTileN;
   return d.channels <= 4 && h2 >= 2 && h2 <= 4 && d.k <= 32 && nt >= 2 && nt <= 3;
@@ -35,11 +73,13 @@ static bool fast_eligible(const bm_desc& d) {
 bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_s* p) {
   XcGeom g;
   fill_geom(d, c.wy, c.wx, c.cap, c.fast, g);
+  if (c.fast) g.p1_step = c.p1;
   if (g.lds_bytes > max_lds)
     return fail(BM_ENOTSUP, "tile needs %d bytes of LDS (limit %d)", g.lds_bytes, max_lds);
   if (c.fast && (!fast_eligible(d) || g.SW > kFastRS))
     return fail(BM_ENOTSUP, "shape outside the specialised kernel");
   p->geom = g;
+  p->cfg = c;
   p->kr = kr_for(d.k);
   hipError_t e;
   if (c.fast) {
@@ -55,30 +95,36 @@ bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_
   return BM_OK;
 }
 
-// Built-in rule: prefer the specialised kernel; take the largest wave grid whose LDS fits
-// and that still gives every CU at least two workgroups, else the configuration with the
-// most workgroups that fits.
-bm_status choose_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
-  // specialised kernel: waves per reference block, largest first that fits the LDS
+// Built-in rule.  Specialised kernel: the most waves per reference block whose LDS fits.
+// Generic kernel: the largest wave grid whose LDS fits and that still gives every CU at
+// least two workgroups, else the configuration with the most workgroups that fits.
+static bm_status builtin_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
   if (fast_eligible(d)) {
     for (int ws : {4, 2, 1}) {
       XcGeom g;
       fill_geom(d, ws, 1, 32, true, g);
-      if (g.lds_bytes <= max_lds && g.SW <= kFastRS)
-        return apply_config(d, TileCfg{ws, 1, 32, true}, max_lds, p);
+      if (g.lds_bytes <= max_lds && g.SW <= kFastRS) {
+        TileCfg c;
+        c.fast = true;
+        c.wy = ws;
+        c.cap = 32;
+        c.p1 = 2;
+        return apply_config(d, c, max_lds, p);
+      }
     }
   }
-  // generic kernel: the largest wave grid whose LDS fits and that still gives every CU at
-  // least two workgroups, else the configuration with the most workgroups that fits
-  static const TileCfg shapes[] = {{2, 2, 64, false}, {1, 2, 64, false}, {2, 1, 64, false},
-                                   {1, 1, 64, false}, {1, 1, 32, false}};
+  static const int shapes[][3] = {{2, 2, 64}, {1, 2, 64}, {2, 1, 64}, {1, 1, 64}, {1, 1, 32}};
   const int min_wg = 512;
-  TileCfg chosen{0, 0, 0, false};
+  TileCfg chosen;
   int chosen_wg = -1;
-  for (const TileCfg& c : shapes) {
+  for (const auto& sh : shapes) {
     XcGeom g;
-    fill_geom(d, c.wy, c.wx, c.cap, false, g);
+    fill_geom(d, sh[0], sh[1], sh[2], false, g);
     if (g.lds_bytes > max_lds) continue;
+    TileCfg c;
+    c.wy = sh[0];
+    c.wx = sh[1];
+    c.cap = sh[2];
     if (g.nwg_total >= min_wg) {
       chosen = c;
       chosen_wg = g.nwg_total;
@@ -91,6 +137,24 @@ bm_status choose_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
   }
   if (chosen_wg < 0) return fail(BM_ENOTSUP, "window/patch/channels too large for LDS");
   return apply_config(d, chosen, max_lds, p);
+}
+
+bool tuned_lookup(const bm_desc& d, TileCfg* out);  // autotuner table (tune.cpp)
+
+bm_status choose_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
+  // explicit override (tuning experiments): honoured only if it applies to this shape
+  const char* env = getenv("BM_CFG");
+  TileCfg c;
+  if (env && parse_cfg(env, &c) && apply_config(d, c, max_lds, p) == BM_OK) {
+    p->cfg_source = 2;
+    return BM_OK;
+  }
+  if (tuned_lookup(d, &c) && apply_config(d, c, max_lds, p) == BM_OK) {
+    p->cfg_source = 1;
+    return BM_OK;
+  }
+  p->cfg_source = 0;
+  return builtin_config(d, max_lds, p);
 }
 
 bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, hipStream_t s) {

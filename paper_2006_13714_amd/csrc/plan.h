@@ -6,15 +6,32 @@
 #include "../../include/bm.h"
 #include "bm_internal.h"
 
+namespace bmk {
+
+// Kernel configuration of a plan.
+struct TileCfg {
+  bool fast = false;  // specialised kernel (C <= 4, patch 3..8, K <= 32, span <= 48 columns)
+  int wy = 1, wx = 1; // generic: wave grid per workgroup; specialised: wy waves per block
+  int cap = 32;       // candidate buffer entries per reference
+  int p1 = 2;         // specialised: bounding-sweep row step
+};
+
+// "fast ws=4 p1=2 cap=32" or "generic wy=2 wx=2 cap=64"; false on a malformed string.
+bool parse_cfg(const char* text, TileCfg* out);
+void format_cfg(const TileCfg& c, char* out, int len);
+
+}  // namespace bmk
+
 struct bm_plan_s {
   bm_desc desc;
   int device = 0;
   bmk::XcGeom geom;
+  bmk::TileCfg cfg;     // configuration in use
   int ks_bucket = 0;    // compiled step count of the generic kernel
   int kr = 1;           // list registers per reference (K <= 16 * kr)
-  void* ws = nullptr;   // plan-owned workspace (norm map, split planes)
+  void* ws = nullptr;   // plan-owned workspace (norm map)
   int64_t ws_bytes = 0;
-  bool tuned = false;   // configuration came from the autotuner's table
+  int cfg_source = 0;   // 0 built-in rule, 1 autotuner table, 2 BM_CFG override
 };
 
 namespace bmk {
@@ -25,12 +42,7 @@ const char* last_error();
 bm_status validate_desc(const bm_desc* d);
 void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g);
 
-// Tile configuration: wave grid per workgroup and candidate-buffer capacity.
-struct TileCfg {
-  int wy, wx, cap;
-  bool fast;  // specialised kernel (C <= 4, patch <= 8, K <= 32, strip fits kFastRS)
-};
-
+bool fast_eligible(const bm_desc& d);
 bm_status choose_config(const bm_desc& d, int max_lds, bm_plan_s* p);
 bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_s* p);
 int64_t plan_workspace_bytes(const bm_plan_s& p);

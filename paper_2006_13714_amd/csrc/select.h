@@ -147,23 +147,25 @@ struct RefSelect {
     }
   }
 
-  // Rows of the sorted lists -> outputs (distance clamped at 0, padding -> (-1, +inf)).
+  // Column v of the sorted lists -> outputs (distance clamped at 0, padding -> (-1, +inf)).
+  __device__ __forceinline__ void write_col(int v, int* out_idx, float* out_dist, size_t ref,
+                                            bool valid) const {
+    if (!valid) return;
+#pragma unroll
+    for (int q = 0; q < KR; ++q) {
+      const int e = 16 * q + p16;
+      if (e < K) {
+        const bool none = Lj[v][q] == kNoIndex;
+        out_idx[ref * K + e] = none ? -1 : Lj[v][q];
+        out_dist[ref * K + e] = none ? INFINITY : fmaxf(Ld[v][q], 0.f);
+      }
+    }
+  }
+
   __device__ __forceinline__ void write(int* out_idx, float* out_dist, const size_t (&ref)[4],
                                         const bool (&valid)[4]) const {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      if (valid[v]) {
-#pragma unroll
-        for (int q = 0; q < KR; ++q) {
-          const int e = 16 * q + p16;
-          if (e < K) {
-            const bool none = Lj[v][q] == kNoIndex;
-            out_idx[ref[v] * K + e] = none ? -1 : Lj[v][q];
-            out_dist[ref[v] * K + e] = none ? INFINITY : fmaxf(Ld[v][q], 0.f);
-          }
-        }
-      }
-    }
+    for (int v = 0; v < 4; ++v) write_col(v, out_idx, out_dist, ref[v], valid[v]);
   }
 };
 

@@ -9,9 +9,9 @@
 // are sorted by a bitonic network and merged into the list by bitonic merges; the 16 largest
 // of (last list register, batch) are dropped.  Unused slots hold (+inf, INT_MAX).
 //
-// Lane exchanges inside a 16-lane row use DPP (xor 1, 2: quad permutes; xor 8: row rotate
-// by 8; xor 15: row mirror) and one ds_swizzle (xor 4), so the networks run at VALU speed
-// instead of paying LDS-crossbar latency per stage.
+// Lane exchanges inside a 16-lane row use DPP only (xor 1, 2: quad permutes; xor 4: row
+// rotates by 4 and 12 selected by lane bit 2; xor 8: row rotate by 8; xor 15: row mirror),
+// so the networks run at VALU speed instead of paying LDS-crossbar latency per stage.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,7 +25,12 @@ template <int M>
 __device__ __forceinline__ int xor_lane(int v) {
   if constexpr (M == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
   else if constexpr (M == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
-  else if constexpr (M == 4) return __builtin_amdgcn_ds_swizzle(v, 0x101F);
+  else if constexpr (M == 4) {
+    // row_ror:N reads lane (i - N) mod 16 of the row
+    const int lo = __builtin_amdgcn_mov_dpp(v, 0x12C, 0xF, 0xF, false);  // lane i + 4
+    const int hi = __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, false);  // lane i - 4
+    return (threadIdx.x & 4) ? hi : lo;
+  }
   else if constexpr (M == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
   else return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false);  // M == 15
 }
@@ -182,6 +187,39 @@ __device__ __forceinline__ void lane_insert(float (&t)[T], float x) {
     t[i] = lo;
   }
   t[T - 1] = fminf(t[T - 1], x);
+}
+
+// Merge an ascending run of 16 (one entry per lane) into the sorted list: the same
+// network as merge_batch without the initial sort.
+template <int KR>
+__device__ __forceinline__ void merge_sorted(float (&Ld)[KR], int (&Lj)[KR], float cd, int cj,
+                                             int p) {
+  cd = xor_lane<15>(cd);  // descending
+  cj = xor_lane<15>(cj);
+  {
+    const bool lt = key_less(Ld[KR - 1], Lj[KR - 1], cd, cj);
+    float sd = lt ? Ld[KR - 1] : cd;
+    int sj = lt ? Lj[KR - 1] : cj;
+    bitonic_merge16(sd, sj, p);
+    cd = sd;
+    cj = sj;
+  }
+#pragma unroll
+  for (int r = 0; r < KR - 1; ++r) {
+    const float rd = xor_lane<15>(cd);
+    const int rj = xor_lane<15>(cj);
+    const bool lt = key_less(Ld[r], Lj[r], rd, rj);
+    float lo_d = lt ? Ld[r] : rd, hi_d = lt ? rd : Ld[r];
+    int lo_j = lt ? Lj[r] : rj, hi_j = lt ? rj : Lj[r];
+    bitonic_merge16(lo_d, lo_j, p);
+    bitonic_merge16(hi_d, hi_j, p);
+    Ld[r] = lo_d;
+    Lj[r] = lo_j;
+    cd = hi_d;
+    cj = hi_j;
+  }
+  Ld[KR - 1] = cd;
+  Lj[KR - 1] = cj;
 }
 
 // Distance of list element K-1 (the admission threshold), broadcast within the row.

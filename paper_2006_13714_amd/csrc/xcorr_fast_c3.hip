@@ -1,0 +1,8 @@
+// Specialised cross-term / top-K kernels for 3 channels (see xcorr_fast.h).
+#include "xcorr_fast.h"
+
+namespace bmk {
+
+XcKernel fast_kernel_c3(int h2, int kr, int nt) { return fast_h2<3>(h2, kr, nt); }
+
+}  // namespace bmk
