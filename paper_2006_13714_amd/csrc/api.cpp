@@ -89,9 +89,15 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) 
   g.NH = (fast ? 0 : 4 * g.s * (wy - 1)) + span;
   g.NW = (fast ? 0 : 4 * g.s * (wx - 1)) + kTileN * g.NT;
   g.NRS = g.NW;
-  g.SH = g.NH + g.Pe - 1;
-  g.SW = g.NW + g.Pe - 1;
-  g.RS = fast ? kFastRS : g.SW;
+  // pixels beyond the patch that the operand reads still touch: the split layout reads whole
+  // 4-row x 8-column blocks (zero weight outside the patch) and they must be staged values
+  const bool split = fast && d.precision != BM_PREC_FP32;
+  const int prow = split ? 4 * ((g.Pe + 3) / 4) : g.Pe;
+  const int pcol = split ? 8 * ((g.Pe + 7) / 8) : g.Pe;
+  g.SH = g.NH + prow - 1;
+  g.SW = g.NW + pcol - 1;
+  g.prec = d.precision;
+  g.RS = fast ? (d.precision == BM_PREC_FP32 ? kFastRS : kSplitRW) : g.SW;
   g.PLANE = g.SH * g.RS;
   g.CAP = cap;
   const int h2 = g.Pe / 2;
@@ -111,7 +117,8 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) 
     g.step_mask[t] = mask;
   }
   const int nw = wy * wx;
-  const int strip_bytes = g.C * g.SH * g.RS * 4;
+  const int rows_per_img_row = (fast && d.precision != BM_PREC_FP32) ? 2 * g.C : g.C;
+  const int strip_bytes = rows_per_img_row * g.SH * g.RS * 4;
   const int norm_bytes = g.NH * g.NRS * 4;
   int buf_bytes = nw * 16 * cap * 8;
   if (fast) {
@@ -203,14 +210,15 @@ bm_status bm_plan_destroy(bm_plan_t plan) {
 bm_status bm_norms(bm_plan_t plan, const float* d_img, float* d_norm, void* stream) {
   if (!plan) return fail(BM_EINVAL, "plan is NULL");
   if (!d_img || !d_norm) return fail(BM_EINVAL, "NULL device pointer");
-  return run_norms(*plan, d_img, d_norm, (hipStream_t)stream);
+  return run_norms(*plan, d_img, d_norm, plan_stats(*plan, plan->ws), (hipStream_t)stream);
 }
 
 bm_status bm_cross_topk(bm_plan_t plan, const float* d_img, const float* d_norm,
                         int32_t* d_idx, float* d_dist, void* stream) {
   if (!plan) return fail(BM_EINVAL, "plan is NULL");
   if (!d_img || !d_norm || !d_idx || !d_dist) return fail(BM_EINVAL, "NULL device pointer");
-  return run_cross_topk(*plan, d_img, d_norm, d_idx, d_dist, (hipStream_t)stream);
+  return run_cross_topk(*plan, d_img, d_norm, plan_stats(*plan, plan->ws), d_idx, d_dist,
+                        (hipStream_t)stream);
 }
 
 bm_status bm_match(bm_plan_t plan, const float* d_img, int32_t* d_idx, float* d_dist,

@@ -12,7 +12,8 @@ constexpr int kMaxSteps = 64;
 constexpr int kMaxK = 64;
 constexpr int kRefBlock = 4;      // a wave owns a 4 x 4 block of references
 constexpr int kTileN = 16;        // candidates per matrix tile (one row segment)
-constexpr int kFastRS = 80;       // LDS row stride (floats) of the specialised kernels
+constexpr int kFastRS = 80;       // LDS row stride (words) of the specialised float32 kernel
+constexpr int kSplitRW = 64;      // LDS row stride (words) of the specialised split kernels
 
 // Geometry of one fused cross-term / distance / top-K launch.  All sizes in elements.
 struct XcGeom {
@@ -37,8 +38,7 @@ struct XcGeom {
   // mask of lane groups (bit g) whose element lies inside the P x P patch (odd P pads).
   int step_off[kMaxSteps];
   uint32_t step_mask[kMaxSteps];
-  // per-channel centring constants (zeros unless BM_FLAG_CENTER)
-  float center[8];
+  int prec;             // BM_PREC_* of the launch
 };
 
 struct NormGeom {

@@ -1,0 +1,249 @@
+// Contraction policies of the specialised cross-term kernel (xcorr_fast.h): how the joint
+// P x P x C patches are laid out in LDS, held in registers and contracted on the matrix cores.
+//
+// Both policies compute, for a tile of 16 references x 16 candidates, the cross terms
+// <X_i, X_j> of Eq. (eq:selfConv) summed over channels (Sec. IV, S(.)), with a float32
+// accumulator.  The strip in LDS holds one image row per channel in consecutive strip rows
+// of RW 32-bit words; a tile's operand-B reads are one base register plus compile-time
+// immediate offsets.
+//
+//  CtF32   float32 products, v_mfma_f32_16x16x4f32; a step covers a 2 x 2 pixel block of one
+//          channel (lane group g holds pixel (g/2, g%2) of the block).
+//  CtSplit x = hi + lo split in bfloat16 (FP16 = false) or float16 after a power-of-two
+//          pre-scale (FP16 = true); three products hi*hi + hi*lo + lo*hi per element on
+//          v_mfma_f32_16x16x32_{bf16,f16}.  A lane holds a 4-row x 2-column pixel block per
+//          32-element block; the strip stores, per pixel x, the 32-bit word (v[x], v[x+1])
+//          of 16-bit parts (rows: channel, then part hi/lo), so every read is aligned.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bm_internal.h"
+
+namespace bmk {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------------------
+template <int C, int H2>
+struct CtF32 {
+  static constexpr int RW = kFastRS;          // words per strip row
+  static constexpr int ROWS = C;              // strip rows per image row
+  static constexpr int CRS = ROWS * RW;       // words per image row
+  static constexpr int NS = C * H2 * H2;      // steps (matrix ops) per tile
+  static constexpr int NB = NS;               // operand-B registers per tile
+  static constexpr bool kScaled = false;
+  using AReg = float;
+
+  // step t = ((l2 * H2) + m2) * C + c: pixels (2*l2 + dy, 2*m2 + dx), dy, dx in {0,1}
+  static constexpr int l2(int t) { return t / (H2 * C); }
+  static constexpr int m2(int t) { return (t / C) % H2; }
+  static constexpr int ch(int t) { return t % C; }
+  static constexpr int off(int t) { return (2 * l2(t) * C + ch(t)) * RW + 2 * m2(t); }
+
+  __device__ static int lane_off(int gp) { return (gp >> 1) * CRS + (gp & 1); }
+
+  // strip rows (y*C + c): the centred image values, zero outside the image
+  __device__ static void stage(uint32_t* strip, const float* img, const XcGeom& g, int SY0,
+                               int SX0, int first, int step, int lane, const float* center,
+                               float) {
+    for (int row = first; row < g.SH * C; row += step) {
+      const int y = row / C;
+      const int c = row - y * C;
+      const int iy = SY0 + y;
+      const bool yok = (iy >= 0) & (iy < g.H);
+      const float cc = center[c];
+      const float* src = img + ((size_t)c * g.H + (yok ? iy : 0)) * g.W;
+      float* dst = reinterpret_cast<float*>(strip) + row * RW;
+      for (int x = lane; x < g.SW; x += 64) {
+        const int ix = SX0 + x;
+        dst[x] = (yok & (ix >= 0) & (ix < g.W)) ? src[ix] - cc : 0.f;
+      }
+    }
+  }
+
+  // operand A for the reference whose patch starts at strip word `base` (lane offset
+  // included); elements outside the P x P patch (odd P) are zero
+  __device__ static void load_a(AReg (&A)[NS], const uint32_t* strip, int base, int gp, int P) {
+    const float* s = reinterpret_cast<const float*>(strip);
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      const bool ok = (2 * l2(t) + (gp >> 1) < P) & (2 * m2(t) + (gp & 1) < P);
+      A[t] = ok ? s[base + off(t)] : 0.f;
+    }
+  }
+
+  __device__ static void load_b(float (&B)[NB], const uint32_t* strip, int base) {
+    const float* s = reinterpret_cast<const float*>(strip);
+#pragma unroll
+    for (int t = 0; t < NB; ++t) B[t] = s[base + off(t)];
+  }
+
+  // the matrix-op chain with the next tile's reads interleaved; `nb` is their base
+  __device__ static f4 chain_and_load(const AReg (&A)[NS], const float (&cur)[NB],
+                                      float (&nxt)[NB], const uint32_t* strip, int nb) {
+    const float* s = reinterpret_cast<const float*>(strip);
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[t], cur[t], acc, 0, 0, 0);
+      nxt[t] = s[nb + off(t)];
+    }
+    return acc;
+  }
+
+  __device__ static void schedule() {
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix op
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // up to two vector ops
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t bf16_rne_bits(float v) {
+  const uint32_t b = __float_as_uint(v);
+  return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+}
+
+template <bool FP16>
+__device__ __forceinline__ void split2(float v, uint32_t& hi, uint32_t& lo) {
+  if constexpr (FP16) {
+    const _Float16 h = (_Float16)v;
+    const _Float16 l = (_Float16)(v - (float)h);
+    hi = __builtin_bit_cast(unsigned short, h);
+    lo = __builtin_bit_cast(unsigned short, l);
+  } else {
+    hi = bf16_rne_bits(v);
+    const float hf = __uint_as_float(hi << 16);
+    lo = bf16_rne_bits(v - hf);
+  }
+}
+
+template <int C, int H2, bool FP16>
+struct CtSplit {
+  static constexpr int RW = kSplitRW;
+  static constexpr int ROWS = 2 * C;          // per image row: channel c -> rows 2c (hi), 2c+1 (lo)
+  static constexpr int CRS = ROWS * RW;
+  static constexpr int PE = 2 * H2;
+  static constexpr int NRB = (PE + 3) / 4;    // 4-row blocks
+  static constexpr int NCB = (PE + 7) / 8;    // 8-column blocks
+  static constexpr int NKB = C * NRB * NCB;   // 32-element blocks
+  static constexpr int NS = 3 * NKB;          // matrix ops per tile
+  static constexpr int NB = 2 * 4 * NKB;      // operand-B words per tile (hi, lo)
+  static constexpr bool kScaled = FP16;
+  using AReg = u4;                            // 8 x 16-bit parts
+
+  // block b = ((rb * NCB) + cb) * C + c; word (part, i) of block b: image row 4*rb + i,
+  // columns 8*cb + 2*g, +1 of channel c
+  static constexpr int rb(int b) { return b / (NCB * C); }
+  static constexpr int cb(int b) { return (b / C) % NCB; }
+  static constexpr int ch(int b) { return b % C; }
+  static constexpr int woff(int b, int part, int i) {
+    return ((4 * rb(b) + i) * ROWS + 2 * ch(b) + part) * RW + 8 * cb(b);
+  }
+
+  __device__ static int lane_off(int gp) { return 2 * gp; }
+
+  __device__ static void stage(uint32_t* strip, const float* img, const XcGeom& g, int SY0,
+                               int SX0, int first, int step, int lane, const float* center,
+                               float scale) {
+    for (int row = first; row < g.SH * C; row += step) {
+      const int y = row / C;
+      const int c = row - y * C;
+      const int iy = SY0 + y;
+      const bool yok = (iy >= 0) & (iy < g.H);
+      const float cc = center[c];
+      const float* src = img + ((size_t)c * g.H + (yok ? iy : 0)) * g.W;
+      uint32_t* dhi = strip + (y * ROWS + 2 * c) * RW;
+      uint32_t* dlo = dhi + RW;
+      for (int x = lane; x < g.SW; x += 64) {
+        const int ix = SX0 + x;
+        const float v0 = (yok & (ix >= 0) & (ix < g.W)) ? (src[ix] - cc) * scale : 0.f;
+        const float v1 = (yok & (ix + 1 >= 0) & (ix + 1 < g.W) & (x + 1 < g.SW))
+                             ? (src[ix + 1] - cc) * scale : 0.f;
+        uint32_t h0, l0, h1, l1;
+        split2<FP16>(v0, h0, l0);
+        split2<FP16>(v1, h1, l1);
+        dhi[x] = h0 | (h1 << 16);
+        dlo[x] = l0 | (l1 << 16);
+      }
+    }
+  }
+
+  // operand A: per block, hi words then lo words; halves outside the P x P patch are zero
+  __device__ static void load_a(AReg (&A)[2 * NKB], const uint32_t* strip, int base, int gp,
+                                int P) {
+#pragma unroll
+    for (int b = 0; b < NKB; ++b) {
+      const int c0 = 8 * cb(b) + 2 * gp;
+      const uint32_t keep = (c0 < P ? 0xFFFFu : 0u) | (c0 + 1 < P ? 0xFFFF0000u : 0u);
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        u4 w;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const bool rok = 4 * rb(b) + i < P;
+          w[i] = rok ? (strip[base + woff(b, part, i)] & keep) : 0u;
+        }
+        A[2 * b + part] = w;
+      }
+    }
+  }
+
+  __device__ static void load_b(uint32_t (&B)[NB], const uint32_t* strip, int base) {
+#pragma unroll
+    for (int b = 0; b < NKB; ++b)
+#pragma unroll
+      for (int part = 0; part < 2; ++part)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) B[(2 * b + part) * 4 + i] = strip[base + woff(b, part, i)];
+  }
+
+  __device__ static f4 mfma(const u4& a, const u4& b, const f4& c) {
+    if constexpr (FP16)
+      return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a),
+                                                    __builtin_bit_cast(h8, b), c, 0, 0, 0);
+    else
+      return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                     __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+  }
+
+  __device__ static f4 chain_and_load(const AReg (&A)[2 * NKB], const uint32_t (&cur)[NB],
+                                      uint32_t (&nxt)[NB], const uint32_t* strip, int nb) {
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < NKB; ++b) {
+      const u4 bhi = {cur[(2 * b) * 4 + 0], cur[(2 * b) * 4 + 1], cur[(2 * b) * 4 + 2],
+                      cur[(2 * b) * 4 + 3]};
+      const u4 blo = {cur[(2 * b + 1) * 4 + 0], cur[(2 * b + 1) * 4 + 1], cur[(2 * b + 1) * 4 + 2],
+                      cur[(2 * b + 1) * 4 + 3]};
+      acc = mfma(A[2 * b], bhi, acc);      // hi * hi
+      acc = mfma(A[2 * b], blo, acc);      // hi * lo
+      acc = mfma(A[2 * b + 1], bhi, acc);  // lo * hi
+#pragma unroll
+      for (int part = 0; part < 2; ++part)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          nxt[(2 * b + part) * 4 + i] = strip[nb + woff(b, part, i)];
+    }
+    return acc;
+  }
+
+  __device__ static void schedule() {
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix op
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // up to two vector ops
+      __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);  // up to three LDS reads
+    }
+  }
+};
+
+}  // namespace bmk

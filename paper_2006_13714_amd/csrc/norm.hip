@@ -1,7 +1,8 @@
 // Patch-norm box filter for gfx950.
 //
 // N[y][x] = sum_c sum_{l<P} sum_{m<P} (X_c[y+l][x+m] - center_c)^2, the entries of
-// h_X (.) h_X (Sec. III-B, the normalisation vector h_X; used by Lemma 2).
+// h_X (.) h_X (Sec. III-B, the normalisation vector h_X; used by Lemma 2).  center_c comes
+// from the statistics pass when centring is on (stats[1 + c]); otherwise it is zero.
 //
 // One workgroup produces a 16 x 64 output tile.  It stages the (16+P-1) x (64+P-1) input
 // window of one channel in LDS with coalesced row loads, forms the horizontal P-tap sums of
@@ -20,10 +21,9 @@ constexpr int kMaxP = 16;
 
 __global__ void __launch_bounds__(256)
 norm_box_kernel(const float* __restrict__ img, float* __restrict__ out, NormGeom g,
-                float c0, float c1, float c2, float c3, float c4, float c5, float c6, float c7) {
+                const float* __restrict__ stats) {
   __shared__ float tile[kNormTY + kMaxP - 1][kNormTX + kMaxP];
   __shared__ double hs[kNormTY + kMaxP - 1][kNormTX];
-  const float centers[8] = {c0, c1, c2, c3, c4, c5, c6, c7};
   const int tx = threadIdx.x & 63;
   const int ty = threadIdx.x >> 6;  // 0..3
   const int ox0 = blockIdx.x * kNormTX;
@@ -34,7 +34,7 @@ norm_box_kernel(const float* __restrict__ img, float* __restrict__ out, NormGeom
 
   for (int c = 0; c < g.C; ++c) {
     const float* plane = img + (size_t)c * g.H * g.W;
-    const float cc = centers[c];
+    const float cc = stats ? stats[1 + c] : 0.f;
     for (int rr = ty; rr < rows; rr += 4) {
       const int y = oy0 + rr;
       for (int xx = tx; xx < cols; xx += 64) {
@@ -71,11 +71,10 @@ norm_box_kernel(const float* __restrict__ img, float* __restrict__ out, NormGeom
   }
 }
 
-hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* center,
+hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* stats,
                        hipStream_t stream) {
   dim3 grid((g.Wv + kNormTX - 1) / kNormTX, (g.Hv + kNormTY - 1) / kNormTY);
-  hipLaunchKernelGGL(norm_box_kernel, grid, dim3(256), 0, stream, img, out, g, center[0],
-                     center[1], center[2], center[3], center[4], center[5], center[6], center[7]);
+  hipLaunchKernelGGL(norm_box_kernel, grid, dim3(256), 0, stream, img, out, g, stats);
   return hipGetLastError();
 }
 

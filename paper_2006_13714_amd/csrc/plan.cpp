@@ -10,15 +10,19 @@
 
 namespace bmk {
 
-hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* center,
+hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* stats,
                        hipStream_t stream);
-hipError_t launch_xcorr_f32(int ks_bucket, int kr, const float* img, const float* nrm, int* idx,
-                            float* dist, const XcGeom& g, hipStream_t stream);
+hipError_t launch_stats(const float* img, int C, int H, int W, bool center, float* stats,
+                        hipStream_t stream);
+hipError_t launch_xcorr_f32(int ks_bucket, int kr, const float* img, const float* nrm,
+                            const float* stats, int* idx, float* dist, const XcGeom& g,
+                            hipStream_t stream);
 int f32_step_bucket(int ks);
 hipError_t prepare_xcorr_f32(int ks_bucket, int kr, int lds_bytes);
-hipError_t prepare_xcorr_fast(int c, int h2, int kr, int nt, int lds_bytes);
-hipError_t launch_xcorr_fast(int c, int h2, int kr, int nt, const float* img, const float* nrm,
-                             int* idx, float* dist, const XcGeom& g, hipStream_t stream);
+hipError_t prepare_xcorr_fast(int prec, int c, int h2, int kr, int nt, int lds_bytes);
+hipError_t launch_xcorr_fast(int prec, int c, int h2, int kr, int nt, const float* img,
+                             const float* nrm, const float* stats, int* idx, float* dist,
+                             const XcGeom& g, hipStream_t stream);
 
 static int kr_for(int k) { return k <= 16 ? 1 : (k <= 32 ? 2 : 4); }
 
@@ -59,15 +63,27 @@ void format_cfg(const TileCfg& c, char* out, int len) {
   else snprintf(out, len, "generic wy=%d wx=%d cap=%d", c.wy, c.wx, c.cap);
 }
 
+// workspace: [norm map (Hv*Wv floats)] [statistics: 9 floats] (256-byte aligned parts)
 int64_t plan_workspace_bytes(const bm_plan_s& p) {
   const XcGeom& g = p.geom;
-  return align256((int64_t)g.Hv * g.Wv * 4);
+  return align256((int64_t)g.Hv * g.Wv * 4) + 256;
+}
+
+bool plan_needs_stats(const bm_plan_s& p) {
+  return (p.desc.flags & BM_FLAG_CENTER) || p.desc.precision == BM_PREC_FP16X3;
+}
+
+float* plan_stats(const bm_plan_s& p, void* ws) {
+  if (!plan_needs_stats(p) || !ws) return nullptr;
+  return reinterpret_cast<float*>(static_cast<char*>(ws) +
+                                  align256((int64_t)p.geom.Hv * p.geom.Wv * 4));
 }
 
 bool fast_eligible(const bm_desc& d) {
   const int h2 = (d.patch + 1) / 2;
   const int nt = (3 * d.stride + 2 * (d.window / 2) + 1 + kTileN - 1) / kTileN;
-  return d.channels <= 4 && h2 >= 2 && h2 <= 4 && d.k <= 32 && nt >= 2 && nt <= 3;
+  const int h2_min = d.precision == BM_PREC_FP32 ? 2 : 3;
+  return d.channels <= 4 && h2 >= h2_min && h2 <= 4 && d.k <= 32 && nt >= 2 && nt <= 3;
 }
 
 bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_s* p) {
@@ -76,15 +92,18 @@ bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_
   if (c.fast) g.p1_step = c.p1;
   if (g.lds_bytes > max_lds)
     return fail(BM_ENOTSUP, "tile needs %d bytes of LDS (limit %d)", g.lds_bytes, max_lds);
-  if (c.fast && (!fast_eligible(d) || g.SW > kFastRS))
+  if (c.fast && (!fast_eligible(d) || g.SW > g.RS))
     return fail(BM_ENOTSUP, "shape outside the specialised kernel");
+  if (!c.fast && d.precision != BM_PREC_FP32)
+    return fail(BM_ENOTSUP, "split precision needs C <= 4, patch 5..8, K <= 32 and "
+                            "3*stride + window <= 48");
   p->geom = g;
   p->cfg = c;
   p->kr = kr_for(d.k);
   hipError_t e;
   if (c.fast) {
     p->ks_bucket = 0;
-    e = prepare_xcorr_fast(d.channels, (d.patch + 1) / 2, p->kr, g.NT, g.lds_bytes);
+    e = prepare_xcorr_fast(d.precision, d.channels, (d.patch + 1) / 2, p->kr, g.NT, g.lds_bytes);
   } else {
     const int bucket = f32_step_bucket(g.KS);
     if (bucket < 0) return fail(BM_ENOTSUP, "no kernel for %d contraction steps", g.KS);
@@ -103,7 +122,7 @@ static bm_status builtin_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
     for (int ws : {4, 2, 1}) {
       XcGeom g;
       fill_geom(d, ws, 1, 32, true, g);
-      if (g.lds_bytes <= max_lds && g.SW <= kFastRS) {
+      if (g.lds_bytes <= max_lds && g.SW <= g.RS) {
         TileCfg c;
         c.fast = true;
         c.wy = ws;
@@ -113,6 +132,9 @@ static bm_status builtin_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
       }
     }
   }
+  if (d.precision != BM_PREC_FP32)
+    return fail(BM_ENOTSUP, "split precision needs C <= 4, patch 5..8, K <= 32 and "
+                            "3*stride + window <= 48 (and the LDS to stage it)");
   static const int shapes[][3] = {{2, 2, 64}, {1, 2, 64}, {2, 1, 64}, {1, 1, 64}, {1, 1, 32}};
   const int min_wg = 512;
   TileCfg chosen;
@@ -157,21 +179,28 @@ bm_status choose_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
   return builtin_config(d, max_lds, p);
 }
 
-bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, hipStream_t s) {
+bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, float* stats,
+                    hipStream_t s) {
   const XcGeom& g = p.geom;
+  hipError_t e;
+  if (stats) {
+    e = launch_stats(d_img, g.C, g.H, g.W, (p.desc.flags & BM_FLAG_CENTER) != 0, stats, s);
+    if (e != hipSuccess) return hip_fail(e, "statistics launch");
+  }
   NormGeom ng{g.H, g.W, g.C, g.P, g.Hv, g.Wv};
-  hipError_t e = launch_norm(d_img, d_norm, ng, g.center, s);
+  e = launch_norm(d_img, d_norm, ng, stats, s);
   if (e != hipSuccess) return hip_fail(e, "norm launch");
   return BM_OK;
 }
 
 bm_status run_cross_topk(const bm_plan_s& p, const float* d_img, const float* d_norm,
-                         int32_t* d_idx, float* d_dist, hipStream_t s) {
+                         const float* stats, int32_t* d_idx, float* d_dist, hipStream_t s) {
   const bm_desc& d = p.desc;
-  hipError_t e = p.geom.fast ? launch_xcorr_fast(d.channels, (d.patch + 1) / 2, p.kr, p.geom.NT,
-                                                 d_img, d_norm, d_idx, d_dist, p.geom, s)
-                             : launch_xcorr_f32(p.ks_bucket, p.kr, d_img, d_norm, d_idx, d_dist,
-                                                p.geom, s);
+  hipError_t e = p.geom.fast
+                     ? launch_xcorr_fast(d.precision, d.channels, (d.patch + 1) / 2, p.kr,
+                                         p.geom.NT, d_img, d_norm, stats, d_idx, d_dist, p.geom, s)
+                     : launch_xcorr_f32(p.ks_bucket, p.kr, d_img, d_norm, stats, d_idx, d_dist,
+                                        p.geom, s);
   if (e != hipSuccess) return hip_fail(e, "cross-term launch");
   return BM_OK;
 }
@@ -180,9 +209,10 @@ bm_status run_match(const bm_plan_s& p, const float* d_img, int32_t* d_idx, floa
                     void* ws, hipStream_t s) {
   if (!ws) return fail(BM_EINVAL, "no workspace");
   float* nrm = static_cast<float*>(ws);
-  bm_status st = run_norms(p, d_img, nrm, s);
+  float* stats = plan_stats(p, ws);
+  bm_status st = run_norms(p, d_img, nrm, stats, s);
   if (st != BM_OK) return st;
-  return run_cross_topk(p, d_img, nrm, d_idx, d_dist, s);
+  return run_cross_topk(p, d_img, nrm, stats, d_idx, d_dist, s);
 }
 
 }  // namespace bmk

@@ -146,6 +146,7 @@ bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, cha
   const int64_t norm_elems = (int64_t)(d.height - d.patch + 1) * (d.width - d.patch + 1);
   float* own_img = nullptr;
   float* nrm = nullptr;
+  float* stats = nullptr;
   int32_t* idx = nullptr;
   float* dist = nullptr;
   hipStream_t s = nullptr;
@@ -154,6 +155,7 @@ bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, cha
   float best_ms = 1e30f;
   auto cleanup = [&]() {
     if (own_img) (void)hipFree(own_img);
+    if (stats) (void)hipFree(stats);
     if (nrm) (void)hipFree(nrm);
     if (idx) (void)hipFree(idx);
     if (dist) (void)hipFree(dist);
@@ -161,7 +163,7 @@ bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, cha
     if (e1) (void)hipEventDestroy(e1);
     if (s) (void)hipStreamDestroy(s);
   };
-  if (hipMalloc(&nrm, norm_elems * 4) != hipSuccess ||
+  if (hipMalloc(&nrm, norm_elems * 4) != hipSuccess || hipMalloc(&stats, 256) != hipSuccess ||
       hipMalloc(&idx, n_ref * d.k * 4) != hipSuccess ||
       hipMalloc(&dist, n_ref * d.k * 4) != hipSuccess) {
     cleanup();
@@ -189,11 +191,13 @@ bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, cha
     p.desc = d;
     p.device = dev;
     if (apply_config(d, c, max_lds, &p) != BM_OK) continue;
-    if (run_norms(p, img, nrm, s) != BM_OK) continue;
-    bool ok = run_cross_topk(p, img, nrm, idx, dist, s) == BM_OK;
+    if (run_norms(p, img, nrm, plan_needs_stats(p) ? stats : nullptr, s) != BM_OK) continue;
+    const float* st = plan_needs_stats(p) ? stats : nullptr;
+    bool ok = run_cross_topk(p, img, nrm, st, idx, dist, s) == BM_OK;
     if (!ok) continue;
     (void)hipEventRecord(e0, s);
-    for (int i = 0; i < reps && ok; ++i) ok = run_cross_topk(p, img, nrm, idx, dist, s) == BM_OK;
+    for (int i = 0; i < reps && ok; ++i)
+      ok = run_cross_topk(p, img, nrm, st, idx, dist, s) == BM_OK;
     (void)hipEventRecord(e1, s);
     if (!ok || hipEventSynchronize(e1) != hipSuccess) continue;
     float ms = 0.f;

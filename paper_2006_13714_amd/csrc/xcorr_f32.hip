@@ -43,7 +43,8 @@ struct Entry {
 template <int KS, int KR>
 __global__ void __launch_bounds__(256)
 xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
-               int* __restrict__ out_idx, float* __restrict__ out_dist, const XcGeom g) {
+               const float* __restrict__ stats, int* __restrict__ out_idx,
+               float* __restrict__ out_dist, const XcGeom g) {
   extern __shared__ __align__(16) unsigned char lds[];
   float* strip = reinterpret_cast<float*>(lds + g.lds_strip_off);
   float* nstrip = reinterpret_cast<float*>(lds + g.lds_norm_off);
@@ -69,7 +70,7 @@ xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
     const int y = row - c * g.SH;
     const int iy = SY0 + y;
     const bool yok = (iy >= 0) & (iy < g.H);
-    const float cc = g.center[c];
+    const float cc = stats ? stats[1 + c] : 0.f;  // centring constant (statistics pass)
     const float* src = img + ((size_t)c * g.H + (yok ? iy : 0)) * g.W;
     float* dst = strip + c * g.PLANE + y * g.RS;
     for (int x = lane; x < g.SW; x += 64) {
@@ -341,7 +342,7 @@ xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
 }
 
 // ---- instantiation table --------------------------------------------------------------
-typedef void (*XcKernel)(const float*, const float*, int*, float*, const XcGeom);
+typedef void (*XcKernel)(const float*, const float*, const float*, int*, float*, const XcGeom);
 
 template <int KS>
 static XcKernel pick_kr(int kr) {
@@ -387,12 +388,13 @@ hipError_t prepare_xcorr_f32(int ks_bucket, int kr, int lds_bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
 }
 
-hipError_t launch_xcorr_f32(int ks_bucket, int kr, const float* img, const float* nrm, int* idx,
-                            float* dist, const XcGeom& g, hipStream_t stream) {
+hipError_t launch_xcorr_f32(int ks_bucket, int kr, const float* img, const float* nrm,
+                            const float* stats, int* idx, float* dist, const XcGeom& g,
+                            hipStream_t stream) {
   XcKernel k = f32_kernel(ks_bucket, kr);
   if (!k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(g.nwg_total), dim3(64 * g.WY * g.WX), g.lds_bytes, stream, img, nrm,
-                     idx, dist, g);
+                     stats, idx, dist, g);
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
-// Fused window-masked cross-correlation + distance assembly + top-K for gfx950 (float32),
-// specialised for C <= 4 channels, patch side 3..8, K <= 32 and a candidate span of
-// NT * 16 columns per 4-reference block.
+// Fused window-masked cross-correlation + distance assembly + top-K for gfx950, specialised
+// for C <= 4 channels, patch side 3..8, K <= 32 and a candidate span of NT * 16 columns per
+// 4-reference block.  The contraction policy (contract.h) selects float32 products or the
+// hi/lo split forms (bfloat16 or float16, three products, float32 accumulation).
 //
 // Per reference X_i and in-window candidate X_j it evaluates Lemma 2 (Sec. III-B),
 //     d_ij = ||X_j||^2 + ||X_i||^2 - 2 <X_i, X_j>,
@@ -13,10 +14,11 @@
 //    interleaved by channel, compile-time row stride) and the norm strip in LDS once.
 //    Candidate rows are dealt round-robin to the S waves, so each wave visits the
 //    candidates of every reference in increasing j.
-//  * Matrix tile: 16 references x 16 candidates (a 16-wide row segment), contracted on
-//    v_mfma_f32_16x16x4f32 in steps of 2 x 2 pixels of one channel.  Operand A (reference
-//    patches) stays in registers; operand B is read from the strip with one base register
-//    per row and immediate offsets (adjacent lanes read adjacent pixels: no im2col).
+//  * Matrix tile: 16 references x 16 candidates (a 16-wide row segment).  Operand A
+//    (reference patches) stays in registers; operand B is read from the strip with one base
+//    register per row and immediate offsets (adjacent lanes read adjacent pixels: no
+//    im2col).  The accumulator of a split form carries the pre-scale squared, which the
+//    distance assembly removes exactly (power of two).
 //  * Window mask: folded into the norms.  ||X_i||^2 is replaced by +inf for tile columns
 //    outside reference i's column range (precomputed per tile column) and ||X_j||^2 by
 //    +inf for rows outside the row range (per row), so an excluded pair has d = +inf.
@@ -31,37 +33,28 @@
 #include <math.h>
 
 #include <type_traits>
+#include <stdint.h>
 
 #include "bm_internal.h"
+#include "contract.h"
 #include "select.h"
 
 namespace bmk {
 
-template <int C, int H2>
-struct FastLayout {
-  static constexpr int RS = kFastRS;
-  static constexpr int CRS = C * RS;  // one image row across the channels
-  static constexpr int KS = C * H2 * H2;
-  // step t = ((l2 * H2) + m2) * C + c covers pixels (2*l2 + dy, 2*m2 + dx), dy, dx in {0,1}
-  static constexpr int l2(int t) { return t / (H2 * C); }
-  static constexpr int m2(int t) { return (t / C) % H2; }
-  static constexpr int ch(int t) { return t % C; }
-  static constexpr int off(int t) { return (2 * l2(t) * C + ch(t)) * RS + 2 * m2(t); }
-};
-
-template <int C, int H2, int KR, int NT>
+template <class CT, int C, int KR, int NT>
 __global__ void __launch_bounds__(256)
 xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
-                int* __restrict__ out_idx, float* __restrict__ out_dist, const XcGeom g) {
-  using L = FastLayout<C, H2>;
-  constexpr int KS = L::KS;
-  constexpr int RS = L::RS;
-  constexpr int CRS = L::CRS;
+                const float* __restrict__ stats, int* __restrict__ out_idx,
+                float* __restrict__ out_dist, const XcGeom g) {
+  constexpr int CRS = CT::CRS;
+  constexpr int NB = CT::NB;
+  using BReg = std::conditional_t<std::is_same_v<typename CT::AReg, float>, float, uint32_t>;
+  constexpr int NA = std::is_same_v<typename CT::AReg, float> ? CT::NS : 2 * (CT::NS / 3);
   constexpr int TL = RefSelect<KR>::TL;
   static_assert(NT >= 1 && NT <= 4, "tile columns");
   constexpr int NW = kTileN * NT;  // norm strip row length
   extern __shared__ __align__(16) unsigned char lds[];
-  float* strip = reinterpret_cast<float*>(lds + g.lds_strip_off);
+  uint32_t* strip = reinterpret_cast<uint32_t*>(lds + g.lds_strip_off);
   float* nstrip = reinterpret_cast<float*>(lds + g.lds_norm_off);
   Entry* buf_all = reinterpret_cast<Entry*>(lds + g.lds_buf_off);
 
@@ -78,21 +71,24 @@ xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
   const int ryw = s * RYw, rxw = s * RXw;  // pixel position of the block's reference (0,0)
   const int SY0 = ryw - r, SX0 = rxw - r;   // strip origin (may be negative)
 
-  // ---- stage the strip (rows y*C + c; zero outside the image) and the norm strip (+inf
-  //      outside the valid positions)
-  for (int row = wave; row < g.SH * C; row += S) {
-    const int y = row / C;
-    const int c = row - y * C;
-    const int iy = SY0 + y;
-    const bool yok = (iy >= 0) & (iy < g.H);
-    const float cc = g.center[c];
-    const float* src = img + ((size_t)c * g.H + (yok ? iy : 0)) * g.W;
-    float* dst = strip + row * RS;
-    for (int x = lane; x < g.SW; x += 64) {
-      const int ix = SX0 + x;
-      dst[x] = (yok & (ix >= 0) & (ix < g.W)) ? src[ix] - cc : 0.f;
-    }
+  // centring constants and the split forms' power-of-two pre-scale (from the statistics
+  // pass: max |x| and per-channel centres); none -> centre 0, scale 1
+  float center[8];
+  float scale = 1.f, mc = -2.f;  // d = mc * acc + (||X_i||^2 + ||X_j||^2)
+#pragma unroll
+  for (int c = 0; c < 8; ++c) center[c] = stats ? stats[1 + c] : 0.f;
+  if (CT::kScaled && stats) {
+    // |x - centre| <= 2 max|x|; keep the scaled magnitude below 2^14 for float16
+    const float m = 2.f * stats[0];
+    const int e = m > 0.f ? ilogbf(m) + 1 : 0;
+    const int k = max(-60, min(60, 14 - e));
+    scale = ldexpf(1.f, k);
+    mc = -2.f * ldexpf(1.f, -2 * k);
   }
+
+  // ---- stage the strip (policy layout; zero outside the image) and the norm strip (+inf
+  //      outside the valid positions)
+  CT::stage(strip, img, g, SY0, SX0, wave, S, lane, center, scale);
   for (int y = wave; y < g.NH; y += S) {
     const int qy = SY0 + y;
     const bool yok = (qy >= 0) & (qy < g.Hv);
@@ -110,19 +106,12 @@ xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
   const int P = g.P, r2 = 2 * r, W = g.W;
   const int p16 = lane & 15;  // operand A row / operand B column / output column
   const int gp = lane >> 4;   // lane group: 2x2 element of a step; output reference row
-  const int lane_off = (gp >> 1) * CRS + (gp & 1);
+  const int lane_off = CT::lane_off(gp);
 
   // ---- operand A: reference i = p16 -> block position (i/4, i%4); zero the padding
   //      elements of odd patch sides
-  float A[KS];
-  {
-    const int base = (s * (p16 >> 2) + r) * CRS + (s * (p16 & 3) + r) + lane_off;
-#pragma unroll
-    for (int t = 0; t < KS; ++t) {
-      const bool ok = (2 * L::l2(t) + (gp >> 1) < P) & (2 * L::m2(t) + (gp & 1) < P);
-      A[t] = ok ? strip[base + L::off(t)] : 0.f;
-    }
-  }
+  typename CT::AReg A[NA];
+  CT::load_a(A, strip, (s * (p16 >> 2) + r) * CRS + (s * (p16 & 3) + r) + lane_off, gp, P);
 
   // ---- selection state for references (row gp, column v); norms with the column part of
   //      the window folded in
@@ -154,37 +143,23 @@ xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
   auto sweep = [&](int first, int stride, auto&& arith, auto&& post) __attribute__((always_inline)) {
     if (first > qy_hi) return;
     const int nrows = (qy_hi - first) / stride + 1;
-    float bufA[KS], bufB[KS];
+    BReg bufA[NB], bufB[NB];
     f4 accp = {0.f, 0.f, 0.f, 0.f};
     // carried description of the previous tile (a virtual +inf row before the first)
     float p_ybias = INFINITY;
     int p_nrow = 0, p_jrow = 0, p_tx = 0;
     int qy = first;
-    {
-      const int rb = (qy - SY0) * CRS + bl;
-#pragma unroll
-      for (int t = 0; t < KS; ++t) bufA[t] = strip[rb + L::off(t)];
-    }
+    CT::load_b(bufA, strip, (qy - SY0) * CRS + bl);
     // tile (qy, TX) with operands in `cur`; loads the next tile into `nxt`
-    auto tile = [&](auto TXc, float (&cur)[KS], float (&nxt)[KS]) __attribute__((always_inline)) {
+    auto tile = [&](auto TXc, BReg (&cur)[NB], BReg (&nxt)[NB]) __attribute__((always_inline)) {
       constexpr int TX = decltype(TXc)::value;
       __builtin_amdgcn_sched_barrier(0);
       const int nqy = (TX + 1 < NT) ? qy : min(qy + stride, qy_hi);
       const int nrb = (nqy - SY0) * CRS + bl + ((TX + 1 < NT) ? kTileN * (TX + 1) : 0);
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int t = 0; t < KS; ++t) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[t], cur[t], acc, 0, 0, 0);
-        nxt[t] = strip[nrb + L::off(t)];
-      }
+      const f4 acc = CT::chain_and_load(A, cur, nxt, strip, nrb);
       const float nc = nstrip[p_nrow + p16 + kTileN * p_tx] + p_ybias;
       auto res = arith(accp, nc, p_tx);
-#pragma unroll
-      for (int t = 0; t < KS; ++t) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix op
-        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // up to two vector ops
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
-      }
+      CT::schedule();
       __builtin_amdgcn_sched_barrier(0);
       post(res, p_jrow + kTileN * p_tx + p16);
       accp = acc;
@@ -238,7 +213,7 @@ xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
               for (int v = 0; v < 4; ++v) nt[v] = nrx[q][v];
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            lane_insert<TL>(sel.tl[v], fmaf(-2.f, acc[v], nt[v] + nc));
+            lane_insert<TL>(sel.tl[v], fmaf(mc, acc[v], nt[v] + nc));
           return 0;
         },
         [&](int, int) __attribute__((always_inline)) {});
@@ -277,7 +252,7 @@ xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
           Admit a;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            a.d[v] = fmaf(-2.f, acc[v], nt[v] + nc);
+            a.d[v] = fmaf(mc, acc[v], nt[v] + nc);
             a.pass[v] = a.d[v] < sel.th[v];
           }
           return a;
@@ -317,33 +292,42 @@ xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
   }
 }
 
-typedef void (*XcKernel)(const float*, const float*, int*, float*, const XcGeom);
+typedef void (*XcFastKernel)(const float*, const float*, const float*, int*, float*,
+                             const XcGeom);
 
-template <int C, int H2, int KR>
-static XcKernel fast_nt(int nt) {
-  switch (nt) {
-    case 2: return xcorr_topk_fast<C, H2, KR, 2>;
-    case 3: return xcorr_topk_fast<C, H2, KR, 3>;
+// policy for (precision, C, H2): 0 float32, 1 bfloat16 split, 2 float16 split
+template <int PREC, int C, int H2>
+using CtFor = std::conditional_t<PREC == 0, CtF32<C, H2>, CtSplit<C, H2, PREC == 2>>;
+
+template <int PREC, int C, int H2, int KR>
+static XcFastKernel fast_nt(int nt) {
+  if constexpr (PREC != 0 && H2 < 3) {
+    return nullptr;  // split forms: patch side 5..8
+  } else {
+    switch (nt) {
+      case 2: return xcorr_topk_fast<CtFor<PREC, C, H2>, C, KR, 2>;
+      case 3: return xcorr_topk_fast<CtFor<PREC, C, H2>, C, KR, 3>;
+    }
+    return nullptr;
   }
-  return nullptr;
 }
 
-template <int C, int H2>
-static XcKernel fast_kr(int kr, int nt) {
+template <int PREC, int C, int H2>
+static XcFastKernel fast_kr(int kr, int nt) {
   switch (kr) {
-    case 1: return fast_nt<C, H2, 1>(nt);
-    case 2: return fast_nt<C, H2, 2>(nt);
+    case 1: return fast_nt<PREC, C, H2, 1>(nt);
+    case 2: return fast_nt<PREC, C, H2, 2>(nt);
   }
   return nullptr;
 }
 
-// All specialised kernels for C channels (one translation unit per C builds in parallel).
-template <int C>
-static XcKernel fast_h2(int h2, int kr, int nt) {
+// All specialised kernels for one (precision, C): each is its own translation unit.
+template <int PREC, int C>
+static XcFastKernel fast_h2(int h2, int kr, int nt) {
   switch (h2) {
-    case 2: return fast_kr<C, 2>(kr, nt);
-    case 3: return fast_kr<C, 3>(kr, nt);
-    case 4: return fast_kr<C, 4>(kr, nt);
+    case 2: return fast_kr<PREC, C, 2>(kr, nt);
+    case 3: return fast_kr<PREC, C, 3>(kr, nt);
+    case 4: return fast_kr<PREC, C, 4>(kr, nt);
   }
   return nullptr;
 }

@@ -5,35 +5,42 @@
 
 namespace bmk {
 
-typedef void (*XcKernel)(const float*, const float*, int*, float*, const XcGeom);
-XcKernel fast_kernel_c1(int h2, int kr, int nt);
-XcKernel fast_kernel_c2(int h2, int kr, int nt);
-XcKernel fast_kernel_c3(int h2, int kr, int nt);
-XcKernel fast_kernel_c4(int h2, int kr, int nt);
+typedef void (*XcFastKernel)(const float*, const float*, const float*, int*, float*,
+                             const XcGeom);
+#define BMK_DECL(P)                                         \
+  XcFastKernel fast_kernel_p##P##_c1(int h2, int kr, int nt); \
+  XcFastKernel fast_kernel_p##P##_c2(int h2, int kr, int nt); \
+  XcFastKernel fast_kernel_p##P##_c3(int h2, int kr, int nt); \
+  XcFastKernel fast_kernel_p##P##_c4(int h2, int kr, int nt);
+BMK_DECL(0)
+BMK_DECL(1)
+BMK_DECL(2)
+#undef BMK_DECL
 
-static XcKernel fast_kernel(int c, int h2, int kr, int nt) {
-  switch (c) {
-    case 1: return fast_kernel_c1(h2, kr, nt);
-    case 2: return fast_kernel_c2(h2, kr, nt);
-    case 3: return fast_kernel_c3(h2, kr, nt);
-    case 4: return fast_kernel_c4(h2, kr, nt);
-  }
-  return nullptr;
+static XcFastKernel fast_kernel(int prec, int c, int h2, int kr, int nt) {
+  typedef XcFastKernel (*Pick)(int, int, int);
+  static const Pick table[3][4] = {
+      {fast_kernel_p0_c1, fast_kernel_p0_c2, fast_kernel_p0_c3, fast_kernel_p0_c4},
+      {fast_kernel_p1_c1, fast_kernel_p1_c2, fast_kernel_p1_c3, fast_kernel_p1_c4},
+      {fast_kernel_p2_c1, fast_kernel_p2_c2, fast_kernel_p2_c3, fast_kernel_p2_c4}};
+  if (prec < 0 || prec > 2 || c < 1 || c > 4) return nullptr;
+  return table[prec][c - 1](h2, kr, nt);
 }
 
-hipError_t prepare_xcorr_fast(int c, int h2, int kr, int nt, int lds_bytes) {
-  XcKernel k = fast_kernel(c, h2, kr, nt);
+hipError_t prepare_xcorr_fast(int prec, int c, int h2, int kr, int nt, int lds_bytes) {
+  XcFastKernel k = fast_kernel(prec, c, h2, kr, nt);
   if (!k) return hipErrorInvalidValue;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                              hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
 }
 
-hipError_t launch_xcorr_fast(int c, int h2, int kr, int nt, const float* img, const float* nrm,
-                             int* idx, float* dist, const XcGeom& g, hipStream_t stream) {
-  XcKernel k = fast_kernel(c, h2, kr, nt);
+hipError_t launch_xcorr_fast(int prec, int c, int h2, int kr, int nt, const float* img,
+                             const float* nrm, const float* stats, int* idx, float* dist,
+                             const XcGeom& g, hipStream_t stream) {
+  XcFastKernel k = fast_kernel(prec, c, h2, kr, nt);
   if (!k) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k, dim3(g.nwg_total), dim3(64 * g.WS), g.lds_bytes, stream, img, nrm, idx,
-                     dist, g);
+  hipLaunchKernelGGL(k, dim3(g.nwg_total), dim3(64 * g.WS), g.lds_bytes, stream, img, nrm, stats,
+                     idx, dist, g);
   return hipGetLastError();
 }
 

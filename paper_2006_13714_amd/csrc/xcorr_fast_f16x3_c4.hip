@@ -1,0 +1,8 @@
+// Specialised cross-term / top-K kernels: precision form f16x3, 4 channels.
+#include "xcorr_fast.h"
+
+namespace bmk {
+
+XcFastKernel fast_kernel_p2_c4(int h2, int kr, int nt) { return fast_h2<2, 4>(h2, kr, nt); }
+
+}  // namespace bmk

@@ -1,0 +1,8 @@
+// Specialised cross-term / top-K kernels: precision form f32, 4 channels.
+#include "xcorr_fast.h"
+
+namespace bmk {
+
+XcFastKernel fast_kernel_p0_c4(int h2, int kr, int nt) { return fast_h2<0, 4>(h2, kr, nt); }
+
+}  // namespace bmk

@@ -1,0 +1,93 @@
+"""Split-precision cross terms and centring against the FP64 oracle.
+
+The float16 form (hi/lo split after a power-of-two pre-scale, three products, float32
+accumulation) is held to the same 1e-4 tolerance as the float32 form.  The bfloat16 form
+keeps about 16 significant bits per operand; its dropped lo*lo term biases near-zero
+distances (self-matches) upward by sum(lo^2), so it is held to a documented looser bound
+and its error is reported.
+"""
+import numpy as np
+import pytest
+
+from paper_2006_13714_amd import synth
+from tests import parity
+from tests.libutil import banner, ensure_built
+
+pytestmark = pytest.mark.gpu
+
+BF16_TOL = 2e-3  # measured ~6e-4 at self-matches on the 512x512 workload
+
+
+def run(x, P, s, Wn, K, precision, flags=0):
+    import torch
+    bm = ensure_built()
+    t = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+    plan = bm.bm_plan(bm.make_desc(t.shape[1], t.shape[2], t.shape[0], P, s, Wn, K, precision, flags))
+    idx = torch.empty((plan.n_ref, K), dtype=torch.int32, device="cuda")
+    dist = torch.empty((plan.n_ref, K), dtype=torch.float32, device="cuda")
+    bm.bm_match(plan, t, idx, dist)
+    torch.cuda.synchronize()
+    plan.close()
+    return idx.cpu().numpy(), dist.cpu().numpy()
+
+
+def sample(n, seed, k=300, head=64):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([rng.choice(n, min(k, n), replace=False), np.arange(min(head, n))]))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp16x3", 1e-4), ("bf16x3", BF16_TOL)])
+@pytest.mark.parametrize("wl", ["gray512", "rgbnir"])
+def test_split_forms(gpu, precision, tol, wl):
+    w = synth.gray512() if wl == "gray512" else synth.rgbnir1024()
+    sh = w.shape
+    banner(f"{w.name} {precision}")
+    idx, dist = run(w.image, sh.patch, sh.stride, sh.window, sh.k, precision)
+    refs = sample(sh.n_ref, 3)
+    rep = parity.check(w.image, sh.patch, sh.stride, sh.window, sh.k, idx[refs], dist[refs], refs=refs, tol=tol)
+    print(precision, wl, rep.summary())
+    assert rep.tolerant_mismatch == 0, (rep.summary(), rep.messages[:4])
+    assert rep.order_violations == 0
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16x3"])
+@pytest.mark.parametrize("seed,C,H,W,P,s,Wn,K", [
+    (11, 1, 70, 83, 8, 3, 31, 16),
+    (12, 3, 64, 50, 6, 3, 25, 32),
+    (13, 2, 45, 61, 7, 2, 21, 9),
+    (14, 4, 40, 40, 5, 4, 29, 20),
+])
+def test_split_edge_shapes(gpu, precision, seed, C, H, W, P, s, Wn, K):
+    banner(f"{precision} edge seed={seed} C={C} H={H} W={W} P={P} s={s} Wn={Wn} K={K}")
+    x = synth.random_image(seed, C, H, W, -1.0, 2.0)
+    idx, dist = run(x, P, s, Wn, K, precision)
+    rep = parity.check(x, P, s, Wn, K, idx, dist)
+    assert rep.tolerant_mismatch == 0, (rep.summary(), rep.messages[:4])
+    assert rep.order_violations == 0
+
+
+def test_fp16_prescale_large_values(gpu):
+    """Values far outside [0, 1]: the power-of-two pre-scale keeps float16 in range."""
+    banner("fp16x3 large values")
+    x = synth.random_image(21, 1, 60, 60, -3000.0, 5000.0)
+    idx, dist = run(x, 8, 3, 21, 16, "fp16x3")
+    rep = parity.check(x, 8, 3, 21, 16, idx, dist)
+    assert rep.tolerant_mismatch == 0, (rep.summary(), rep.messages[:4])
+
+
+def test_centering_keeps_results_translation_invariant(gpu):
+    """With centring on, adding a constant to the image leaves the distances unchanged
+    (up to float32 rounding) and the sets identical."""
+    banner("centring translation invariance")
+    x = synth.gray_voronoi(5, 96, 96)
+    i0, d0 = run(x, 8, 3, 21, 16, "fp32", flags=1)
+    i1, d1 = run(x + 7.0, 8, 3, 21, 16, "fp32", flags=1)
+    assert np.mean(i0 == i1) > 0.99
+    np.testing.assert_allclose(d1, d0, rtol=2e-3, atol=2e-3)
+
+
+def test_split_unsupported_shape_is_enotsup(gpu):
+    bm = ensure_built()
+    with pytest.raises(bm.BMError) as ei:
+        bm.bm_plan(bm.make_desc(64, 64, 1, 3, 1, 9, 16, "fp16x3"))  # patch 3: outside the split envelope
+    assert ei.value.status == bm.BM_ENOTSUP
