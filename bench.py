@@ -7,10 +7,13 @@ Workload: one 512x512 grayscale float32 image (Voronoi cells + noise sigma 50/25
 the patch-norm box filter (bm_norms) followed by the fused cross-term / distance / top-K
 kernel (bm_cross_topk); the two calls together are exactly bm_match.
 
-Output: one JSON line.  `value` is ref-patches/s of the reported form over the timed
-region (inputs already in HBM); `roofline` covers the dominant kernel (the cross-term
-kernel), timed with HIP events on its own launch stream; `cpu_baseline` times the FP64
-oracle on a bounded sample on this host.
+Output: one JSON line.  Every precision form is timed (plain float32, bfloat16 split,
+float16 split); `value` is ref-patches/s of the reported form (default: the float16 split,
+the fastest form that meets the float32 accuracy bound) over the timed region with the
+inputs already in HBM, and `plain_fp32` gives the plain float32 form beside it.
+`roofline` covers the dominant kernel (the cross-term kernel of the reported form), timed
+with HIP events on its own launch stream; `cpu_baseline` times the FP64 oracle on a bounded
+sample on this host.
 """
 from __future__ import annotations
 
@@ -27,11 +30,8 @@ sys.path.insert(0, ROOT)
 METRIC = "ref patches/s (top-16, 8x8 patch, 39x39 window) vs plain FP32; p50/p99 latency"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "fp16x3": 2500.0}  # dense matrix-core peaks
 DTYPE = {"fp32": "f32", "bf16x3": "bf16x3->f32", "fp16x3": "f16x3->f32"}
-KERNEL_SOURCES = {
-    "fp32": ["xcorr_f32.hip", "topk.h", "bm_internal.h"],
-    "bf16x3": ["xcorr_split.hip", "topk.h", "bm_internal.h"],
-    "fp16x3": ["xcorr_split.hip", "topk.h", "bm_internal.h"],
-}
+_FAST = ["xcorr_fast.h", "contract.h", "select.h", "topk.h", "bm_internal.h"]
+KERNEL_SOURCES = {"fp32": _FAST, "bf16x3": _FAST, "fp16x3": _FAST}
 
 
 def source_hash(prec: str) -> str:
@@ -139,7 +139,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precision", default="fp32", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--precision", default="fp16x3", choices=list(PEAK_TFLOPS))
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle work for the CPU baseline (0 disables it)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -170,8 +170,7 @@ def main():
         torch.cuda.synchronize()
 
     results = {}
-    forms = ["fp32"] if args.precision == "fp32" else ["fp32", args.precision]
-    for prec in forms:
+    for prec in ["fp32", "bf16x3", "fp16x3"]:
         results[prec] = run_form(bm, torch, img_t, sh, prec, args.steps, args.warmup)
 
     prec = args.precision
@@ -210,10 +209,16 @@ def main():
                      "kernel": f"xcorr_topk ({prec})",
                      "algorithmic_flops_per_launch": flops},
     }
-    if prec != "fp32":
-        p32, wall32, *_ = results["fp32"]
-        v32 = p32.n_ref * args.steps / wall32
-        out["plain_fp32"] = {"value": v32, "speedup": value / v32}
+    forms = {}
+    for f, (pf, wf, nf, xf, sf, _) in results.items():
+        xa = sum(xf) / len(xf) / 1e3
+        forms[f] = {"value": pf.n_ref * args.steps / wf, "ms_per_step": wf / args.steps * 1e3,
+                    "cross_topk_ms": xa * 1e3, "p50_ms": quantile(sf, 0.5),
+                    "p99_ms": quantile(sf, 0.99), "config": bm.bm_plan_config(pf)[0],
+                    "roofline_frac": flops / xa / 1e12 / PEAK_TFLOPS[f]}
+    out["forms"] = forms
+    v32 = forms["fp32"]["value"]
+    out["plain_fp32"] = {"value": v32, "speedup": value / v32}
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(w.image, sh, args.cpu_budget)
     print(json.dumps(out), flush=True)
