@@ -1,6 +1,9 @@
 """Build libbm.so (HIP kernels for gfx950 + the C-ABI host code) in-tree.
 
-Usage: python -m paper_2006_13714_amd.build_lib [-j N]
+Usage: python -m paper_2006_13714_amd.build_lib [-j N] [--incremental]
+
+By default every source is compiled.  With --incremental an object is reused when it is
+newer than its source and every header of the library.
 """
 from __future__ import annotations
 
@@ -34,11 +37,22 @@ def hipcc() -> str:
 
 
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
+    # kernel translation units first: they take longest
+    srcs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp"))]
+    return sorted(srcs, key=lambda p: (not os.path.basename(p).startswith("xcorr"), p))
 
 
-def _compile(src: str) -> str:
+def _headers_mtime() -> float:
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    hs += [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return max(os.path.getmtime(h) for h in hs)
+
+
+def _compile(src: str, incremental: bool = False, hdr_mtime: float = 0.0) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj) and \
+            os.path.getmtime(obj) > max(os.path.getmtime(src), hdr_mtime):
+        return obj
     cmd = [hipcc(), *COMMON, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -46,12 +60,13 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
+def build(jobs: int | None = None, verbose: bool = False, incremental: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(8, os.cpu_count() or 1)
     srcs = sources()
+    hm = _headers_mtime()
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda p: _compile(p, incremental, hm), srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -66,6 +81,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true")
     a = ap.parse_args()
-    build(a.j, verbose=True)
+    build(a.j, verbose=True, incremental=a.incremental)
     sys.exit(0)

@@ -32,14 +32,31 @@ struct XcGeom {
   int CAP;              // candidate buffer entries per reference
   int KS;               // real k-steps (the rest of the template's steps are zero-padded)
   int lds_strip_off, lds_norm_off, lds_buf_off, lds_bytes;
-  // split forms: element scale applied before the split (power of two) and its inverse^2
-  float pre_scale, post_scale;
   // k-step table: LDS offset of each step relative to a patch's top-left corner, and the
   // mask of lane groups (bit g) whose element lies inside the P x P patch (odd P pads).
   int step_off[kMaxSteps];
   uint32_t step_mask[kMaxSteps];
   int prec;             // BM_PREC_* of the launch
 };
+
+// The fields of XcGeom that the specialised kernel reads (kernel argument of the
+// single-image launch; per-image record of the batch launch).
+struct FastGeom {
+  int H, W, Hv, Wv, P, s, r, K;
+  int nry, nrx, nwg_x, nwg_total;
+  int SH, SW, NH, CAP, p1_step;
+  int lds_strip_off, lds_norm_off, lds_buf_off;
+};
+
+inline FastGeom fast_geom(const XcGeom& g) {
+  FastGeom f;
+  f.H = g.H; f.W = g.W; f.Hv = g.Hv; f.Wv = g.Wv; f.P = g.P; f.s = g.s; f.r = g.r; f.K = g.K;
+  f.nry = g.nry; f.nrx = g.nrx; f.nwg_x = g.nwg_x; f.nwg_total = g.nwg_total;
+  f.SH = g.SH; f.SW = g.SW; f.NH = g.NH; f.CAP = g.CAP; f.p1_step = g.p1_step;
+  f.lds_strip_off = g.lds_strip_off; f.lds_norm_off = g.lds_norm_off;
+  f.lds_buf_off = g.lds_buf_off;
+  return f;
+}
 
 struct NormGeom {
   int H, W, C, P, Hv, Wv;

@@ -48,7 +48,7 @@ struct CtF32 {
   __device__ static int lane_off(int gp) { return (gp >> 1) * CRS + (gp & 1); }
 
   // strip rows (y*C + c): the centred image values, zero outside the image
-  __device__ static void stage(uint32_t* strip, const float* img, const XcGeom& g, int SY0,
+  __device__ static void stage(uint32_t* strip, const float* img, const FastGeom& g, int SY0,
                                int SX0, int first, int step, int lane, const float* center,
                                float) {
     for (int row = first; row < g.SH * C; row += step) {
@@ -151,7 +151,7 @@ struct CtSplit {
 
   __device__ static int lane_off(int gp) { return 2 * gp; }
 
-  __device__ static void stage(uint32_t* strip, const float* img, const XcGeom& g, int SY0,
+  __device__ static void stage(uint32_t* strip, const float* img, const FastGeom& g, int SY0,
                                int SX0, int first, int step, int lane, const float* center,
                                float scale) {
     for (int row = first; row < g.SH * C; row += step) {

@@ -2,7 +2,7 @@
 //
 // N[y][x] = sum_c sum_{l<P} sum_{m<P} (X_c[y+l][x+m] - center_c)^2, the entries of
 // h_X (.) h_X (Sec. III-B, the normalisation vector h_X; used by Lemma 2).  center_c comes
-// from the statistics pass when centring is on (stats[1 + c]); otherwise it is zero.
+// from the centring pass when centring is on (centers[c]); otherwise it is zero.
 //
 // One workgroup produces a 16 x 64 output tile.  It stages the (16+P-1) x (64+P-1) input
 // window of one channel in LDS with coalesced row loads, forms the horizontal P-tap sums of
@@ -10,7 +10,12 @@
 // (no prefix or summed-area tables, whose rounding grows with the image) and carried in
 // float64, so every output is the float32 rounding of the exact norm.  HBM-bound: each
 // input element is read once from HBM and each output written once.
+//
+// The batch form covers many images in one launch: workgroup b finds its image by a
+// binary search over the images' first tile numbers.
 #include <hip/hip_runtime.h>
+
+#include "batch.h"
 #include "bm_internal.h"
 
 namespace bmk {
@@ -19,46 +24,49 @@ constexpr int kNormTX = 64;
 constexpr int kNormTY = 16;
 constexpr int kMaxP = 16;
 
-__global__ void __launch_bounds__(256)
-norm_box_kernel(const float* __restrict__ img, float* __restrict__ out, NormGeom g,
-                const float* __restrict__ stats) {
-  __shared__ float tile[kNormTY + kMaxP - 1][kNormTX + kMaxP];
-  __shared__ double hs[kNormTY + kMaxP - 1][kNormTX];
+struct NormLds {
+  float tile[kNormTY + kMaxP - 1][kNormTX + kMaxP];
+  double hs[kNormTY + kMaxP - 1][kNormTX];
+};
+
+__device__ __forceinline__ void norm_tile(const float* __restrict__ img, float* __restrict__ out,
+                                          const NormGeom& g, const float* __restrict__ centers,
+                                          int bx, int by, NormLds& sh) {
   const int tx = threadIdx.x & 63;
   const int ty = threadIdx.x >> 6;  // 0..3
-  const int ox0 = blockIdx.x * kNormTX;
-  const int oy0 = blockIdx.y * kNormTY;
+  const int ox0 = bx * kNormTX;
+  const int oy0 = by * kNormTY;
   const int rows = kNormTY + g.P - 1;
   const int cols = kNormTX + g.P - 1;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 
   for (int c = 0; c < g.C; ++c) {
     const float* plane = img + (size_t)c * g.H * g.W;
-    const float cc = stats ? stats[1 + c] : 0.f;
+    const float cc = centers ? centers[c] : 0.f;
     for (int rr = ty; rr < rows; rr += 4) {
       const int y = oy0 + rr;
       for (int xx = tx; xx < cols; xx += 64) {
         const int x = ox0 + xx;
         float v = 0.f;
         if (y < g.H && x < g.W) v = plane[(size_t)y * g.W + x] - cc;
-        tile[rr][xx] = v;
+        sh.tile[rr][xx] = v;
       }
     }
     __syncthreads();
     for (int rr = ty; rr < rows; rr += 4) {
       double s = 0.0;
       for (int m = 0; m < g.P; ++m) {
-        const double v = (double)tile[rr][tx + m];
+        const double v = (double)sh.tile[rr][tx + m];
         s += v * v;
       }
-      hs[rr][tx] = s;
+      sh.hs[rr][tx] = s;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int row = ty * 4 + k;
       double s = 0.0;
-      for (int l = 0; l < g.P; ++l) s += hs[row + l][tx];
+      for (int l = 0; l < g.P; ++l) s += sh.hs[row + l][tx];
       acc[k] += s;
     }
     __syncthreads();
@@ -71,10 +79,50 @@ norm_box_kernel(const float* __restrict__ img, float* __restrict__ out, NormGeom
   }
 }
 
-hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* stats,
+__global__ void __launch_bounds__(256)
+norm_box_kernel(const float* __restrict__ img, float* __restrict__ out, NormGeom g,
+                const float* __restrict__ centers) {
+  __shared__ NormLds sh;
+  norm_tile(img, out, g, centers, blockIdx.x, blockIdx.y, sh);
+}
+
+__global__ void __launch_bounds__(256)
+norm_box_batch_kernel(const BatchNorm* __restrict__ items, int n, unsigned* __restrict__ counters,
+                      int n_counters) {
+  __shared__ NormLds sh;
+  // the persistent cross-term launches that follow on the stream start from zero
+  if (blockIdx.x == 0 && (int)threadIdx.x < n_counters) counters[threadIdx.x] = 0u;
+  const int b = blockIdx.x;
+  int lo = 0, hi = n - 1;  // last image whose first tile is <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (load_uniform(&items[mid].tile_begin) <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchNorm it = load_uniform(&items[lo]);
+  const int t = b - it.tile_begin;
+  const int ty = t / it.tiles_x;
+  norm_tile(it.img, it.out, it.g, it.centers, t - ty * it.tiles_x, ty, sh);
+}
+
+void norm_tiles(const NormGeom& g, int* tiles_x, int* tiles_y) {
+  *tiles_x = (g.Wv + kNormTX - 1) / kNormTX;
+  *tiles_y = (g.Hv + kNormTY - 1) / kNormTY;
+}
+
+hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* centers,
                        hipStream_t stream) {
-  dim3 grid((g.Wv + kNormTX - 1) / kNormTX, (g.Hv + kNormTY - 1) / kNormTY);
-  hipLaunchKernelGGL(norm_box_kernel, grid, dim3(256), 0, stream, img, out, g, stats);
+  int tx, ty;
+  norm_tiles(g, &tx, &ty);
+  hipLaunchKernelGGL(norm_box_kernel, dim3(tx, ty), dim3(256), 0, stream, img, out, g, centers);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_batch(const BatchNorm* d_items, int n, int total_tiles,
+                             unsigned* d_counters, int n_counters, hipStream_t stream) {
+  if (n < 1 || total_tiles < 1 || n_counters > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(norm_box_batch_kernel, dim3(total_tiles), dim3(256), 0, stream, d_items, n,
+                     d_counters, n_counters);
   return hipGetLastError();
 }
 

@@ -10,18 +10,18 @@
 
 namespace bmk {
 
-hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* stats,
+hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* centers,
                        hipStream_t stream);
-hipError_t launch_stats(const float* img, int C, int H, int W, bool center, float* stats,
-                        hipStream_t stream);
+hipError_t launch_centers(const float* img, int C, int H, int W, float* centers,
+                          hipStream_t stream);
 hipError_t launch_xcorr_f32(int ks_bucket, int kr, const float* img, const float* nrm,
-                            const float* stats, int* idx, float* dist, const XcGeom& g,
+                            const float* centers, int* idx, float* dist, const XcGeom& g,
                             hipStream_t stream);
 int f32_step_bucket(int ks);
 hipError_t prepare_xcorr_f32(int ks_bucket, int kr, int lds_bytes);
 hipError_t prepare_xcorr_fast(int prec, int c, int h2, int kr, int nt, int lds_bytes);
 hipError_t launch_xcorr_fast(int prec, int c, int h2, int kr, int nt, const float* img,
-                             const float* nrm, const float* stats, int* idx, float* dist,
+                             const float* nrm, const float* centers, int* idx, float* dist,
                              const XcGeom& g, hipStream_t stream);
 
 static int kr_for(int k) { return k <= 16 ? 1 : (k <= 32 ? 2 : 4); }
@@ -63,18 +63,16 @@ void format_cfg(const TileCfg& c, char* out, int len) {
   else snprintf(out, len, "generic wy=%d wx=%d cap=%d", c.wy, c.wx, c.cap);
 }
 
-// workspace: [norm map (Hv*Wv floats)] [statistics: 9 floats] (256-byte aligned parts)
+// workspace: [norm map (Hv*Wv floats)] [centring constants: 8 floats] (256-byte aligned)
 int64_t plan_workspace_bytes(const bm_plan_s& p) {
   const XcGeom& g = p.geom;
   return align256((int64_t)g.Hv * g.Wv * 4) + 256;
 }
 
-bool plan_needs_stats(const bm_plan_s& p) {
-  return (p.desc.flags & BM_FLAG_CENTER) || p.desc.precision == BM_PREC_FP16X3;
-}
+bool plan_needs_centers(const bm_plan_s& p) { return (p.desc.flags & BM_FLAG_CENTER) != 0; }
 
-float* plan_stats(const bm_plan_s& p, void* ws) {
-  if (!plan_needs_stats(p) || !ws) return nullptr;
+float* plan_centers(const bm_plan_s& p, void* ws) {
+  if (!plan_needs_centers(p) || !ws) return nullptr;
   return reinterpret_cast<float*>(static_cast<char*>(ws) +
                                   align256((int64_t)p.geom.Hv * p.geom.Wv * 4));
 }
@@ -179,27 +177,27 @@ bm_status choose_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
   return builtin_config(d, max_lds, p);
 }
 
-bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, float* stats,
+bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, float* centers,
                     hipStream_t s) {
   const XcGeom& g = p.geom;
   hipError_t e;
-  if (stats) {
-    e = launch_stats(d_img, g.C, g.H, g.W, (p.desc.flags & BM_FLAG_CENTER) != 0, stats, s);
-    if (e != hipSuccess) return hip_fail(e, "statistics launch");
+  if (centers) {
+    e = launch_centers(d_img, g.C, g.H, g.W, centers, s);
+    if (e != hipSuccess) return hip_fail(e, "centring launch");
   }
   NormGeom ng{g.H, g.W, g.C, g.P, g.Hv, g.Wv};
-  e = launch_norm(d_img, d_norm, ng, stats, s);
+  e = launch_norm(d_img, d_norm, ng, centers, s);
   if (e != hipSuccess) return hip_fail(e, "norm launch");
   return BM_OK;
 }
 
 bm_status run_cross_topk(const bm_plan_s& p, const float* d_img, const float* d_norm,
-                         const float* stats, int32_t* d_idx, float* d_dist, hipStream_t s) {
+                         const float* centers, int32_t* d_idx, float* d_dist, hipStream_t s) {
   const bm_desc& d = p.desc;
   hipError_t e = p.geom.fast
                      ? launch_xcorr_fast(d.precision, d.channels, (d.patch + 1) / 2, p.kr,
-                                         p.geom.NT, d_img, d_norm, stats, d_idx, d_dist, p.geom, s)
-                     : launch_xcorr_f32(p.ks_bucket, p.kr, d_img, d_norm, stats, d_idx, d_dist,
+                                         p.geom.NT, d_img, d_norm, centers, d_idx, d_dist, p.geom, s)
+                     : launch_xcorr_f32(p.ks_bucket, p.kr, d_img, d_norm, centers, d_idx, d_dist,
                                         p.geom, s);
   if (e != hipSuccess) return hip_fail(e, "cross-term launch");
   return BM_OK;
@@ -209,10 +207,10 @@ bm_status run_match(const bm_plan_s& p, const float* d_img, int32_t* d_idx, floa
                     void* ws, hipStream_t s) {
   if (!ws) return fail(BM_EINVAL, "no workspace");
   float* nrm = static_cast<float*>(ws);
-  float* stats = plan_stats(p, ws);
-  bm_status st = run_norms(p, d_img, nrm, stats, s);
+  float* centers = plan_centers(p, ws);
+  bm_status st = run_norms(p, d_img, nrm, centers, s);
   if (st != BM_OK) return st;
-  return run_cross_topk(p, d_img, nrm, stats, d_idx, d_dist, s);
+  return run_cross_topk(p, d_img, nrm, centers, d_idx, d_dist, s);
 }
 
 }  // namespace bmk

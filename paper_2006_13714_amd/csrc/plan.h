@@ -46,14 +46,14 @@ bool fast_eligible(const bm_desc& d);
 bm_status choose_config(const bm_desc& d, int max_lds, bm_plan_s* p);
 bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_s* p);
 int64_t plan_workspace_bytes(const bm_plan_s& p);
-// statistics slot (centres, max |x|) inside a workspace, or NULL if the plan needs none
-bool plan_needs_stats(const bm_plan_s& p);
-float* plan_stats(const bm_plan_s& p, void* ws);
-// norms (and, when the plan needs them, the statistics first into `stats`)
-bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, float* stats,
+// centring constants slot inside a workspace, or NULL if the plan does not centre
+bool plan_needs_centers(const bm_plan_s& p);
+float* plan_centers(const bm_plan_s& p, void* ws);
+// norms (and, when the plan centres, the centring constants first into `centers`)
+bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, float* centers,
                     hipStream_t s);
 bm_status run_cross_topk(const bm_plan_s& p, const float* d_img, const float* d_norm,
-                         const float* stats, int32_t* d_idx, float* d_dist, hipStream_t s);
+                         const float* centers, int32_t* d_idx, float* d_dist, hipStream_t s);
 bm_status run_match(const bm_plan_s& p, const float* d_img, int32_t* d_idx, float* d_dist,
                     void* ws, hipStream_t s);
 

@@ -1,17 +1,10 @@
-// Batch and serving entry points (filled in by their own sources).
+// Serving entry points (filled in by their own source).
 #include "plan.h"
 
 using namespace bmk;
 
 extern "C" {
 
-bm_status bm_batch_workspace(int32_t, const bm_plan_t*, int64_t*) {
-  return fail(BM_ENOTSUP, "batch path not built");
-}
-bm_status bm_match_batch(int32_t, const bm_plan_t*, const float* const*, int32_t* const*,
-                         float* const*, void*, void*) {
-  return fail(BM_ENOTSUP, "batch path not built");
-}
 bm_status bm_server_create(const bm_server_cfg*, bm_server_t*) {
   return fail(BM_ENOTSUP, "server not built");
 }

@@ -191,8 +191,8 @@ bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, cha
     p.desc = d;
     p.device = dev;
     if (apply_config(d, c, max_lds, &p) != BM_OK) continue;
-    if (run_norms(p, img, nrm, plan_needs_stats(p) ? stats : nullptr, s) != BM_OK) continue;
-    const float* st = plan_needs_stats(p) ? stats : nullptr;
+    if (run_norms(p, img, nrm, plan_needs_centers(p) ? stats : nullptr, s) != BM_OK) continue;
+    const float* st = plan_needs_centers(p) ? stats : nullptr;
     bool ok = run_cross_topk(p, img, nrm, st, idx, dist, s) == BM_OK;
     if (!ok) continue;
     (void)hipEventRecord(e0, s);

@@ -1,0 +1,8 @@
+// Persistent uneven-batch kernels: precision form bf16x3, K <= 16, 2 tile columns.
+#include "xcorr_batch.h"
+
+namespace bmk {
+
+XcBatchKernel batch_kernel_p1_k1_t2(int tier) { return batch_tier<1, 1, 2>(tier); }
+
+}  // namespace bmk

@@ -1,0 +1,8 @@
+// Persistent uneven-batch kernels: precision form bf16x3, K <= 16, 3 tile columns.
+#include "xcorr_batch.h"
+
+namespace bmk {
+
+XcBatchKernel batch_kernel_p1_k1_t3(int tier) { return batch_tier<1, 1, 3>(tier); }
+
+}  // namespace bmk

@@ -43,7 +43,7 @@ struct Entry {
 template <int KS, int KR>
 __global__ void __launch_bounds__(256)
 xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
-               const float* __restrict__ stats, int* __restrict__ out_idx,
+               const float* __restrict__ centers, int* __restrict__ out_idx,
                float* __restrict__ out_dist, const XcGeom g) {
   extern __shared__ __align__(16) unsigned char lds[];
   float* strip = reinterpret_cast<float*>(lds + g.lds_strip_off);
@@ -70,7 +70,7 @@ xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
     const int y = row - c * g.SH;
     const int iy = SY0 + y;
     const bool yok = (iy >= 0) & (iy < g.H);
-    const float cc = stats ? stats[1 + c] : 0.f;  // centring constant (statistics pass)
+    const float cc = centers ? centers[c] : 0.f;  // centring constant
     const float* src = img + ((size_t)c * g.H + (yok ? iy : 0)) * g.W;
     float* dst = strip + c * g.PLANE + y * g.RS;
     for (int x = lane; x < g.SW; x += 64) {
@@ -389,12 +389,12 @@ hipError_t prepare_xcorr_f32(int ks_bucket, int kr, int lds_bytes) {
 }
 
 hipError_t launch_xcorr_f32(int ks_bucket, int kr, const float* img, const float* nrm,
-                            const float* stats, int* idx, float* dist, const XcGeom& g,
+                            const float* centers, int* idx, float* dist, const XcGeom& g,
                             hipStream_t stream) {
   XcKernel k = f32_kernel(ks_bucket, kr);
   if (!k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(g.nwg_total), dim3(64 * g.WY * g.WX), g.lds_bytes, stream, img, nrm,
-                     stats, idx, dist, g);
+                     centers, idx, dist, g);
   return hipGetLastError();
 }
 

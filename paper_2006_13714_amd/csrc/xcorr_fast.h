@@ -41,11 +41,37 @@
 
 namespace bmk {
 
+// max |x - centre| over the in-image pixels of the strip rows first, first + step, ...
+// (this thread's share; rows are image rows x channels as in the policies' staging)
+template <int C>
+__device__ __forceinline__ float strip_absmax(const float* __restrict__ img, const FastGeom& g,
+                                              int SY0, int SX0, int first, int step, int lane,
+                                              const float* center) {
+  float m = 0.f;
+  for (int row = first; row < g.SH * C; row += step) {
+    const int y = row / C;
+    const int c = row - y * C;
+    const int iy = SY0 + y;
+    if ((iy < 0) | (iy >= g.H)) continue;
+    const float* src = img + ((size_t)c * g.H + iy) * g.W;
+    for (int x = lane; x < g.SW; x += 64) {
+      const int ix = SX0 + x;
+      if ((ix >= 0) & (ix < g.W)) m = fmaxf(m, fabsf(src[ix] - center[c]));
+    }
+  }
+  return m;
+}
+
+// One 4 x 4 reference block `blk` (row-major over the block grid) of one image, computed by
+// the whole workgroup (blockDim.x / 64 waves).  `centers` holds the per-channel centring
+// constants or is null.  Every thread of the workgroup must call it (it synchronises).
 template <class CT, int C, int KR, int NT>
-__global__ void __launch_bounds__(256)
-xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
-                const float* __restrict__ stats, int* __restrict__ out_idx,
-                float* __restrict__ out_dist, const XcGeom g) {
+__device__ __forceinline__ void fast_block(const float* __restrict__ img,
+                                           const float* __restrict__ nrm,
+                                           const float* __restrict__ centers,
+                                           int* __restrict__ out_idx,
+                                           float* __restrict__ out_dist, const FastGeom& g,
+                                           int blk, unsigned char* lds) {
   constexpr int CRS = CT::CRS;
   constexpr int NB = CT::NB;
   using BReg = std::conditional_t<std::is_same_v<typename CT::AReg, float>, float, uint32_t>;
@@ -53,7 +79,6 @@ xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
   constexpr int TL = RefSelect<KR>::TL;
   static_assert(NT >= 1 && NT <= 4, "tile columns");
   constexpr int NW = kTileN * NT;  // norm strip row length
-  extern __shared__ __align__(16) unsigned char lds[];
   uint32_t* strip = reinterpret_cast<uint32_t*>(lds + g.lds_strip_off);
   float* nstrip = reinterpret_cast<float*>(lds + g.lds_norm_off);
   Entry* buf_all = reinterpret_cast<Entry*>(lds + g.lds_buf_off);
@@ -63,7 +88,6 @@ xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int S = blockDim.x >> 6;  // waves sharing the reference block
 
-  const int blk = xcd_remap(blockIdx.x, g.nwg_total);
   const int by = blk / g.nwg_x;
   const int bx = blk - by * g.nwg_x;
   const int s = g.s, r = g.r;
@@ -71,16 +95,23 @@ xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
   const int ryw = s * RYw, rxw = s * RXw;  // pixel position of the block's reference (0,0)
   const int SY0 = ryw - r, SX0 = rxw - r;   // strip origin (may be negative)
 
-  // centring constants and the split forms' power-of-two pre-scale (from the statistics
-  // pass: max |x| and per-channel centres); none -> centre 0, scale 1
+  // centring constants; the float16 form's power-of-two pre-scale 2^k keeps the largest
+  // staged magnitude of this block's strip below 2^14, and the distance assembly removes
+  // it exactly (factor 2^-2k)
   float center[8];
   float scale = 1.f, mc = -2.f;  // d = mc * acc + (||X_i||^2 + ||X_j||^2)
 #pragma unroll
-  for (int c = 0; c < 8; ++c) center[c] = stats ? stats[1 + c] : 0.f;
-  if (CT::kScaled && stats) {
-    // |x - centre| <= 2 max|x|; keep the scaled magnitude below 2^14 for float16
-    const float m = 2.f * stats[0];
-    const int e = m > 0.f ? ilogbf(m) + 1 : 0;
+  for (int c = 0; c < 8; ++c) center[c] = (centers && c < C) ? centers[c] : 0.f;
+  if constexpr (CT::kScaled) {
+    float m = strip_absmax<C>(img, g, SY0, SX0, wave, S, lane, center);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    float* red = reinterpret_cast<float*>(buf_all);
+    if (lane == 0) red[wave] = m;
+    __syncthreads();
+    m = red[0];
+    for (int w = 1; w < S; ++w) m = fmaxf(m, red[w]);
+    const int e = m > 0.f ? ilogbf(m) + 1 : 0;  // m < 2^e
     const int k = max(-60, min(60, 14 - e));
     scale = ldexpf(1.f, k);
     mc = -2.f * ldexpf(1.f, -2 * k);
@@ -292,8 +323,19 @@ xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
   }
 }
 
+// Single image: one workgroup per reference block, XCD-aware block order.
+template <class CT, int C, int KR, int NT>
+__global__ void __launch_bounds__(256)
+xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
+                const float* __restrict__ centers, int* __restrict__ out_idx,
+                float* __restrict__ out_dist, const FastGeom g) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  fast_block<CT, C, KR, NT>(img, nrm, centers, out_idx, out_dist, g,
+                            xcd_remap(blockIdx.x, g.nwg_total), lds);
+}
+
 typedef void (*XcFastKernel)(const float*, const float*, const float*, int*, float*,
-                             const XcGeom);
+                             const FastGeom);
 
 // policy for (precision, C, H2): 0 float32, 1 bfloat16 split, 2 float16 split
 template <int PREC, int C, int H2>

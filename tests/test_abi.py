@@ -76,3 +76,20 @@ def test_null_arguments():
     assert lib.bm_match(None, None, None, None, None, None) == bm.BM_EINVAL
     assert lib.bm_plan_destroy(None) == bm.BM_EINVAL
     assert "NULL" in bm.bm_last_error()
+
+
+def test_batch_arguments_checked_on_host():
+    import ctypes as C
+    bm = ensure_built()
+    lib = bm.lib()
+    # an empty batch is a no-op and needs no workspace
+    assert lib.bm_match_batch(0, None, None, None, None, None, None) == bm.BM_OK
+    out = C.c_int64(-1)
+    assert lib.bm_batch_workspace(0, None, C.byref(out)) == bm.BM_OK and out.value == 0
+    assert lib.bm_match_batch(-1, None, None, None, None, None, None) == bm.BM_EINVAL
+    assert lib.bm_match_batch(2, None, None, None, None, None, None) == bm.BM_EINVAL
+    nulls = (C.c_void_p * 2)(None, None)
+    assert lib.bm_match_batch(2, nulls, nulls, nulls, nulls, None, None) == bm.BM_EINVAL
+    assert "NULL" in bm.bm_last_error()
+    assert lib.bm_batch_workspace(2, nulls, C.byref(out)) == bm.BM_EINVAL
+    assert lib.bm_batch_workspace(1, nulls, None) == bm.BM_EINVAL
