@@ -93,3 +93,20 @@ def test_batch_arguments_checked_on_host():
     assert "NULL" in bm.bm_last_error()
     assert lib.bm_batch_workspace(2, nulls, C.byref(out)) == bm.BM_EINVAL
     assert lib.bm_batch_workspace(1, nulls, None) == bm.BM_EINVAL
+
+
+def test_server_arguments_checked_on_host():
+    import ctypes as C
+    bm = ensure_built()
+    lib = bm.lib()
+    out = C.c_void_p()
+    assert lib.bm_server_create(None, C.byref(out)) == bm.BM_EINVAL
+    bad = bm.bm_server_cfg(0, 1, 1)  # budget below the minimum
+    assert lib.bm_server_create(C.byref(bad), C.byref(out)) == bm.BM_EINVAL
+    bad = bm.bm_server_cfg(1 << 30, 0, 1)
+    assert lib.bm_server_create(C.byref(bad), C.byref(out)) == bm.BM_EINVAL
+    t = C.c_uint64()
+    assert lib.bm_submit(None, None, None, C.byref(t)) == bm.BM_EINVAL
+    assert lib.bm_poll(None, 1, None, None, None) == bm.BM_EINVAL
+    assert lib.bm_cancel(None, 1) == bm.BM_EINVAL
+    assert lib.bm_server_destroy(None) == bm.BM_EINVAL
