@@ -14,6 +14,13 @@ inputs already in HBM, and `plain_fp32` gives the plain float32 form beside it.
 `roofline` covers the dominant kernel (the cross-term kernel of the reported form), timed
 with HIP events on its own launch stream; `cpu_baseline` times the FP64 oracle on a bounded
 sample on this host.
+
+Other workloads (not the headline line; one JSON line each):
+  --workload batch64   64 images of uneven shapes (sides 128..1024, C in {1,3}, P in {6,8})
+                       through bm_match_batch, against 64 single-image bm_match calls.
+  --workload serving   Poisson request streams at the --qps rates (sides log-uniform in
+                       [256, 2048], 1..4 channels) through bm_submit / bm_poll: achieved
+                       ref-patches/s and p50/p99 request latency per rate.
 """
 from __future__ import annotations
 
@@ -144,6 +151,11 @@ def main():
                     help="seconds of oracle work for the CPU baseline (0 disables it)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 64 MiB device copy (counter calibration)")
+    ap.add_argument("--workload", default="gray512", choices=["gray512", "batch64", "serving"])
+    ap.add_argument("--qps", default="50,200,500,1000,2000",
+                    help="serving: comma-separated request rates")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="serving: length of each rate's request stream")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -157,6 +169,10 @@ def main():
     if not os.path.exists(bm.LIB_PATH):
         from paper_2006_13714_amd import build_lib
         build_lib.build()
+    if args.workload == "batch64":
+        return bench_batch(args, bm, synth, torch)
+    if args.workload == "serving":
+        return bench_serving(args, bm, synth, torch)
 
     w = synth.gray512()
     sh = w.shape
@@ -221,6 +237,185 @@ def main():
     out["plain_fp32"] = {"value": v32, "speedup": value / v32}
     if args.cpu_budget > 0:
         out["cpu_baseline"] = cpu_baseline(w.image, sh, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args, bm, synth, torch):
+    """The 64-image uneven workload: one bm_match_batch call per step."""
+    import numpy as np
+    ws = synth.uneven_batch(64)
+    ts = [torch.from_numpy(w.image).to("cuda:0") for w in ws]
+    n_ref = sum(w.shape.n_ref for w in ws)
+    flops = sum(2.0 * w.shape.patch ** 2 * w.shape.channels *
+                pair_count(w.shape.height, w.shape.width, w.shape.patch, w.shape.stride,
+                           w.shape.window) for w in ws)
+    stream = torch.cuda.current_stream()
+    forms = {}
+    steps = max(3, min(args.steps, 20))
+    for prec in ["fp32", "bf16x3", "fp16x3"]:
+        plans = [bm.cached_plan(bm.make_desc(w.shape.height, w.shape.width, w.shape.channels,
+                                             w.shape.patch, w.shape.stride, w.shape.window,
+                                             w.shape.k, prec)) for w in ws]
+        idxs = [torch.empty((p.n_ref, 16), dtype=torch.int32, device="cuda:0") for p in plans]
+        dists = [torch.empty((p.n_ref, 16), dtype=torch.float32, device="cuda:0") for p in plans]
+        wsb = torch.empty((bm.bm_batch_workspace(plans),), dtype=torch.uint8, device="cuda:0")
+
+        def one_batch():
+            bm.bm_match_batch(plans, ts, idxs, dists, wsb, stream)
+
+        def per_image():
+            for p, t, i, d in zip(plans, ts, idxs, dists):
+                bm.bm_match(p, t, i, d, None, stream)
+
+        res = {}
+        for name, fn in (("batch", one_batch), ("per_image", per_image)):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(steps)]
+            t0 = time.perf_counter()
+            for a, b in ev:
+                a.record(stream)
+                fn()
+                b.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ms = [a.elapsed_time(b) for a, b in ev]
+            res[name] = {"value": n_ref * steps / wall, "ms_per_step": wall / steps * 1e3,
+                         "p50_ms": quantile(ms, 0.5), "p99_ms": quantile(ms, 0.99)}
+        forms[prec] = {"batch": res["batch"], "per_image": res["per_image"],
+                       "configs": sorted({bm.bm_plan_config(p)[0] for p in plans})}
+    prec = args.precision
+    v = forms[prec]["batch"]["value"]
+    step_s = forms[prec]["batch"]["ms_per_step"] / 1e3
+    achieved = flops / step_s / 1e12
+    out = {
+        "metric": METRIC, "value": v, "unit": "ref-patches/s", "n_gpus": 1, "steps": steps,
+        "warmup": 2, "ms_per_step": forms[prec]["batch"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": "uneven_batch64", "images": len(ws), "n_ref": n_ref,
+                   "precision": prec, "seed0": 1000},
+        "latency_ms": {"p50": forms[prec]["batch"]["p50_ms"], "p99": forms[prec]["batch"]["p99_ms"]},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec],
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,
+                     "kernel": "whole batch step (norms + persistent cross-term launches)",
+                     "algorithmic_flops_per_launch": flops},
+        "forms": forms,
+        "plain_fp32": {"value": forms["fp32"]["per_image"]["value"],
+                       "speedup": v / forms["fp32"]["per_image"]["value"]},
+    }
+    if args.cpu_budget > 0:
+        out["cpu_baseline"] = cpu_baseline_batch(ws, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batch(ws, budget_s):
+    """FP64 oracle on 24 seeded references of each image in turn (bounded by budget_s)."""
+    import numpy as np
+    from oracle import bm_oracle as O
+    rng = np.random.default_rng(5)
+    done = 0
+    t0 = time.perf_counter()
+    for w in ws:
+        refs = np.sort(rng.choice(w.shape.n_ref, size=min(24, w.shape.n_ref), replace=False))
+        O.bm(w.image, w.shape.patch, w.shape.stride, w.shape.window, w.shape.k, refs=refs)
+        done += len(refs)
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "ref-patches/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} references (24 seeded per image, images in order) of the "
+                      f"64-image batch, numpy float64 brute force, {dt:.1f} s"}
+
+
+def bench_serving(args, bm, synth, torch):
+    """Poisson request streams through the serving loop, one rate after another."""
+    import threading
+    import numpy as np
+    pool = [w for _, w in synth.serving_requests(16, 100.0)]
+    prec = args.precision
+    rates = [float(q) for q in args.qps.split(",") if q]
+    sweep = []
+    for qps in rates:
+        rng = np.random.default_rng(int(qps) + 17)
+        n = max(8, int(qps * args.serve_seconds))
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, size=n))
+        arrivals -= arrivals[0]
+        srv = bm.bm_server_create(32 << 30, max_inflight=64, max_queue=4096)
+        outstanding = {}
+        stats = []
+        rejected = 0
+        lock = threading.Lock()
+        stop = threading.Event()
+
+        def poller():
+            bufs = {}
+            while not stop.is_set() or outstanding:
+                with lock:
+                    items = list(outstanding.items())
+                if not items:
+                    time.sleep(0.0002)
+                    continue
+                for t, (w, d) in items:
+                    st, s = bm.bm_poll(srv, t)
+                    if st == bm.BM_OK:
+                        with lock:
+                            del outstanding[t]
+                        stats.append((s.total_s, s.queue_s, s.device_s, s.n_ref, time.perf_counter()))
+                time.sleep(0.0002)
+
+        # warm: one request of each channel count
+        for w in pool[:4]:
+            d = bm.make_desc(w.shape.height, w.shape.width, w.shape.channels, 8, 3, 39, 16, prec)
+            t = bm.bm_submit(srv, d, w.image)
+            while bm.bm_poll(srv, t)[0] != bm.BM_OK:
+                time.sleep(0.001)
+        th = threading.Thread(target=poller)
+        th.start()
+        t_start = time.perf_counter()
+        offered = 0
+        for i in range(n):
+            w = pool[i % len(pool)]
+            delay = t_start + arrivals[i] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            d = bm.make_desc(w.shape.height, w.shape.width, w.shape.channels, 8, 3, 39, 16, prec)
+            offered += w.shape.n_ref
+            try:
+                t = bm.bm_submit(srv, d, w.image)
+                with lock:
+                    outstanding[t] = (w, d)
+            except bm.BMError as e:
+                if e.status != bm.BM_EBUSY:
+                    raise
+                rejected += 1
+        t_submitted = time.perf_counter()
+        stop.set()
+        th.join()
+        bm.bm_server_destroy(srv)
+        t_end = max(s[4] for s in stats) if stats else t_submitted
+        done_refs = sum(s[3] for s in stats)
+        tot = sorted(s[0] for s in stats)
+        sweep.append({"qps": qps, "requests": n, "completed": len(stats), "rejected": rejected,
+                      "offered_refs_per_s": offered / max(arrivals[-1], 1e-9),
+                      "achieved_refs_per_s": done_refs / (t_end - t_start),
+                      "p50_ms": 1e3 * quantile(tot, 0.5), "p99_ms": 1e3 * quantile(tot, 0.99),
+                      "queue_p50_ms": 1e3 * quantile(sorted(s[1] for s in stats), 0.5),
+                      "device_p50_ms": 1e3 * quantile(sorted(s[2] for s in stats), 0.5)})
+        print(json.dumps({"serving_level": sweep[-1]}), file=sys.stderr, flush=True)
+    best = max(sweep, key=lambda r: r["achieved_refs_per_s"])
+    out = {
+        "metric": METRIC, "value": best["achieved_refs_per_s"], "unit": "ref-patches/s",
+        "n_gpus": 1, "steps": sum(r["completed"] for r in sweep), "warmup": 4,
+        "ms_per_step": best["p50_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[prec], "data": "synthetic",
+        "config": {"workload": "serving_poisson", "precision": prec, "pool": len(pool),
+                   "sides": "log-uniform 256..2048", "channels": "1..4", "qps": rates},
+        "latency_ms": {"p50": best["p50_ms"], "p99": best["p99_ms"]},
+        "sweep": sweep,
+    }
     print(json.dumps(out), flush=True)
 
 

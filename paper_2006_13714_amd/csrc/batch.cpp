@@ -40,7 +40,7 @@ static XcBatchKernel batch_kernel(int prec, int kr, int nt, int tier) {
       {{batch_kernel_p0_k1_t2, batch_kernel_p0_k1_t3}, {batch_kernel_p0_k2_t2, batch_kernel_p0_k2_t3}},
       {{batch_kernel_p1_k1_t2, batch_kernel_p1_k1_t3}, {batch_kernel_p1_k2_t2, batch_kernel_p1_k2_t3}},
       {{batch_kernel_p2_k1_t2, batch_kernel_p2_k1_t3}, {batch_kernel_p2_k2_t2, batch_kernel_p2_k2_t3}}};
-  if (prec < 0 || prec > 2 || kr < 1 || kr > 2 || nt < 2 || nt > 3 || tier < 0 || tier > 1)
+  if (prec < 0 || prec > 2 || kr < 1 || kr > 2 || nt < 2 || nt > 3 || tier < 0 || tier > 2)
     return nullptr;
   return table[prec][kr - 1][nt - 2](tier);
 }
@@ -146,7 +146,7 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
       generic.push_back(b);
       continue;
     }
-    const int tier = p.desc.channels == 4 ? 1 : 0;
+    const int tier = batch_tier(p.desc.precision, p.desc.channels);
     auto key = std::make_tuple(p.desc.precision, p.kr, p.geom.NT, tier);
     Group& g = groups[key];
     g.prec = p.desc.precision;
@@ -174,10 +174,20 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
     std::stable_sort(g.members.begin(), g.members.end(), [&](int a, int b) {
       return block_cost(*e[a].plan) > block_cost(*e[b].plan);
     });
-    // waves per block: the smallest of the members' tuned values (fewer waves need less
-    // LDS, so every member's layout still fits)
-    g.ws = 4;
-    for (int b : g.members) g.ws = std::min(g.ws, e[b].plan->cfg.wy);
+    // waves per block: the largest of the members' tuned values that the group's kernel
+    // takes and at which every member's LDS layout fits
+    int want = 1;
+    for (int b : g.members) want = std::max(want, e[b].plan->cfg.wy);
+    g.ws = std::min(want, batch_max_waves(g.tier));
+    for (; g.ws > 1; g.ws >>= 1) {
+      bool fits = true;
+      for (int b : g.members) {
+        XcGeom t;
+        fill_geom(e[b].plan->desc, g.ws, 1, e[b].plan->cfg.cap, true, t);
+        fits &= t.lds_bytes <= max_lds;
+      }
+      if (fits) break;
+    }
     g.rec_off = rec;
     for (int b : g.members) {
       const bm_plan_s& p = *e[b].plan;

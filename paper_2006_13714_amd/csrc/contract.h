@@ -37,6 +37,7 @@ struct CtF32 {
   static constexpr int NS = C * H2 * H2;      // steps (matrix ops) per tile
   static constexpr int NB = NS;               // operand-B registers per tile
   static constexpr bool kScaled = false;
+  static constexpr bool kSplit = false;
   using AReg = float;
 
   // step t = ((l2 * H2) + m2) * C + c: pixels (2*l2 + dy, 2*m2 + dx), dy, dx in {0,1}
@@ -138,6 +139,7 @@ struct CtSplit {
   static constexpr int NS = 3 * NKB;          // matrix ops per tile
   static constexpr int NB = 2 * 4 * NKB;      // operand-B words per tile (hi, lo)
   static constexpr bool kScaled = FP16;
+  static constexpr bool kSplit = true;
   using AReg = u4;                            // 8 x 16-bit parts
 
   // block b = ((rb * NCB) + cb) * C + c; word (part, i) of block b: image row 4*rb + i,

@@ -50,8 +50,8 @@ bool parse_cfg(const char* text, TileCfg* out) {
   }
   while (*p == ' ') ++p;
   if (*p) return false;
-  if (c.wy < 1 || c.wx < 1 || c.wy * c.wx > 4 || c.cap < 32 || c.cap > 256 || (c.cap & 15) ||
-      c.p1 < 1 || c.p1 > 8)
+  if (c.wy < 1 || c.wx < 1 || c.wy * c.wx > (c.fast ? 8 : 4) || c.cap < 32 || c.cap > 256 ||
+      (c.cap & 15) || c.p1 < 1 || c.p1 > 8)
     return false;
   if (c.fast && c.wx != 1) return false;
   *out = c;
@@ -92,6 +92,8 @@ bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_
     return fail(BM_ENOTSUP, "tile needs %d bytes of LDS (limit %d)", g.lds_bytes, max_lds);
   if (c.fast && (!fast_eligible(d) || g.SW > g.RS))
     return fail(BM_ENOTSUP, "shape outside the specialised kernel");
+  if (c.fast && c.wy > fast_max_waves(d.precision, d.channels))
+    return fail(BM_ENOTSUP, "%d waves per block exceed this kernel's limit", c.wy);
   if (!c.fast && d.precision != BM_PREC_FP32)
     return fail(BM_ENOTSUP, "split precision needs C <= 4, patch 5..8, K <= 32 and "
                             "3*stride + window <= 48");
@@ -112,12 +114,14 @@ bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_
   return BM_OK;
 }
 
-// Built-in rule.  Specialised kernel: the most waves per reference block whose LDS fits.
+// Built-in rule.  Specialised kernel: the most waves per reference block (up to the
+// kernel's limit) whose LDS fits.
 // Generic kernel: the largest wave grid whose LDS fits and that still gives every CU at
 // least two workgroups, else the configuration with the most workgroups that fits.
 static bm_status builtin_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
   if (fast_eligible(d)) {
-    for (int ws : {4, 2, 1}) {
+    for (int ws : {8, 4, 2, 1}) {
+      if (ws > fast_max_waves(d.precision, d.channels)) continue;
       XcGeom g;
       fill_geom(d, ws, 1, 32, true, g);
       if (g.lds_bytes <= max_lds && g.SW <= g.RS) {

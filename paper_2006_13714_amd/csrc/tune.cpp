@@ -99,9 +99,10 @@ __global__ void tune_image_kernel(float* img, int C, int H, int W) {
 static std::vector<TileCfg> candidates(const bm_desc& d) {
   std::vector<TileCfg> v;
   if (fast_eligible(d)) {
-    for (int ws : {1, 2, 4})
+    for (int ws : {1, 2, 4, 8})
       for (int p1 : {1, 2, 3, 4})
         for (int cap : {32, 64}) {
+          if (ws > fast_max_waves(d.precision, d.channels)) continue;
           TileCfg c;
           c.fast = true;
           c.wy = ws;

@@ -8,11 +8,11 @@
 // its image's geometry and per-image tuned parameters (bounding-sweep row step, buffer
 // capacity); the shape class (channels, patch side) selects the compiled body.
 //
-// A kernel's register count, and with it how many workgroups a compute unit keeps, is the
-// maximum over the bodies compiled into it, and four-channel bodies need the most.  Each
-// (precision, K class, tile columns) therefore has two kernels: tier 0 holds the bodies for
-// 1..3 channels, tier 1 those for 4 channels; a batch without 4-channel images is one
-// launch.
+// A kernel's register count and workgroup shape, and with them how many workgroups a
+// compute unit keeps, are shared by every body compiled into it.  The bodies are therefore
+// grouped in tiers of similar shape (batch_tier): float32 tier 0 holds 1..3 channels, the
+// split forms' tier 0 one channel and tier 2 two or three channels (8-wave blocks), and
+// tier 1 four channels.  A batch runs one persistent launch per tier present.
 #pragma once
 
 #include "batch.h"
@@ -33,12 +33,19 @@ __device__ __forceinline__ void batch_block(const BatchXc& r, int blk, unsigned 
 
 template <int PREC, int KR, int NT, int TIER, int C, int H2>
 __device__ __forceinline__ void batch_tier_block(const BatchXc& r, int blk, unsigned char* lds) {
-  if constexpr ((TIER == 0) == (C <= 3)) batch_block<PREC, KR, NT, C, H2>(r, blk, lds);
+  if constexpr (batch_tier(PREC, C) == TIER) batch_block<PREC, KR, NT, C, H2>(r, blk, lds);
   else (void)r, (void)blk, (void)lds;
 }
 
+// waves per SIMD the compiler must leave room for: float32 tier 0 mixes 1- and 3-channel
+// bodies and keeps two; the 8-wave tier needs two per SIMD by construction
+constexpr int batch_min_waves(int prec, int tier) {
+  return tier == 1 ? 1 : ((prec == 0 || tier == 2) ? 2 : 1);
+}
+
 template <int PREC, int KR, int NT, int TIER>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TIER == 0 ? 2 : 1)))
+__global__ void __launch_bounds__(64 * batch_max_waves(TIER))
+__attribute__((amdgpu_waves_per_eu(batch_min_waves(PREC, TIER))))
 xcorr_topk_batch(const BatchXc* __restrict__ recs, int n_recs, int n_items,
                  unsigned* __restrict__ counter) {
   extern __shared__ __align__(16) unsigned char lds[];
@@ -79,10 +86,13 @@ xcorr_topk_batch(const BatchXc* __restrict__ recs, int n_recs, int n_items,
 typedef void (*XcBatchKernel)(const BatchXc*, int, int, unsigned*);
 
 template <int PREC, int KR, int NT>
-static XcBatchKernel batch_tier(int tier) {
+static XcBatchKernel batch_tier_kernel(int tier) {
   switch (tier) {
     case 0: return xcorr_topk_batch<PREC, KR, NT, 0>;
     case 1: return xcorr_topk_batch<PREC, KR, NT, 1>;
+    case 2:
+      if constexpr (PREC != 0) return xcorr_topk_batch<PREC, KR, NT, 2>;
+      break;
   }
   return nullptr;
 }

@@ -3,6 +3,6 @@
 
 namespace bmk {
 
-XcBatchKernel batch_kernel_p1_k1_t2(int tier) { return batch_tier<1, 1, 2>(tier); }
+XcBatchKernel batch_kernel_p1_k1_t2(int tier) { return batch_tier_kernel<1, 1, 2>(tier); }
 
 }  // namespace bmk

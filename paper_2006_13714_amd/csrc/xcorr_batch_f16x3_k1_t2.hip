@@ -3,6 +3,6 @@
 
 namespace bmk {
 
-XcBatchKernel batch_kernel_p2_k1_t2(int tier) { return batch_tier<2, 1, 2>(tier); }
+XcBatchKernel batch_kernel_p2_k1_t2(int tier) { return batch_tier_kernel<2, 1, 2>(tier); }
 
 }  // namespace bmk

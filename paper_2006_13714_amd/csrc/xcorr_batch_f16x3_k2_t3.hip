@@ -3,6 +3,6 @@
 
 namespace bmk {
 
-XcBatchKernel batch_kernel_p2_k2_t3(int tier) { return batch_tier<2, 2, 3>(tier); }
+XcBatchKernel batch_kernel_p2_k2_t3(int tier) { return batch_tier_kernel<2, 2, 3>(tier); }
 
 }  // namespace bmk

@@ -3,6 +3,6 @@
 
 namespace bmk {
 
-XcBatchKernel batch_kernel_p0_k1_t3(int tier) { return batch_tier<0, 1, 3>(tier); }
+XcBatchKernel batch_kernel_p0_k1_t3(int tier) { return batch_tier_kernel<0, 1, 3>(tier); }
 
 }  // namespace bmk

@@ -3,6 +3,6 @@
 
 namespace bmk {
 
-XcBatchKernel batch_kernel_p0_k2_t2(int tier) { return batch_tier<0, 2, 2>(tier); }
+XcBatchKernel batch_kernel_p0_k2_t2(int tier) { return batch_tier_kernel<0, 2, 2>(tier); }
 
 }  // namespace bmk

@@ -325,7 +325,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
 
 // Single image: one workgroup per reference block, XCD-aware block order.
 template <class CT, int C, int KR, int NT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * fast_max_waves(CT::kSplit ? 1 : 0, C))
 xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
                 const float* __restrict__ centers, int* __restrict__ out_idx,
                 float* __restrict__ out_dist, const FastGeom g) {
