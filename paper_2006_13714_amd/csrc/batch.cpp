@@ -107,6 +107,32 @@ struct Group {
 };
 }  // namespace
 
+// Workgroups of `k` one compute unit keeps at this size and LDS; raises the kernel's
+// dynamic-LDS limit first.  Both are remembered per (kernel, device, size, LDS), so
+// repeated batches (the serving loop) make no driver calls for them.
+static hipError_t resident_blocks(const void* k, int dev, int threads, int lds, int* per_cu) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, int, int, int>, int> known;
+  static std::map<std::pair<const void*, int>, int> lds_set;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_tuple(k, dev, threads, lds);
+  auto it = known.find(key);
+  if (it != known.end()) {
+    *per_cu = it->second;
+    return hipSuccess;
+  }
+  int& cur = lds_set[std::make_pair(k, dev)];
+  if (lds > cur) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    cur = lds;
+  }
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, threads, lds);
+  if (e != hipSuccess) return e;
+  known[key] = *per_cu;
+  return hipSuccess;
+}
+
 static int shape_class(const bm_desc& d) { return (d.channels - 1) * 3 + ((d.patch + 1) / 2 - 2); }
 
 // contraction work per reference block, up to a common factor
@@ -248,13 +274,9 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
     Group& g = kv.second;
     XcBatchKernel k = batch_kernel(g.prec, g.kr, g.nt, g.tier);
     if (!k) return fail(BM_ENOTSUP, "no persistent kernel for this group");
-    he = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, g.lds);
-    if (he != hipSuccess) return hip_fail(he, "hipFuncSetAttribute");
     int per_cu = 0;
-    he = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k),
-                                                      64 * g.ws, g.lds);
-    if (he != hipSuccess) return hip_fail(he, "occupancy query");
+    he = resident_blocks(reinterpret_cast<const void*>(k), dev, 64 * g.ws, g.lds, &per_cu);
+    if (he != hipSuccess) return hip_fail(he, "persistent kernel set-up");
     if (per_cu < 1) return fail(BM_ENOTSUP, "persistent kernel does not fit a compute unit");
     const int grid = std::min(g.items, per_cu * n_cu);
     hipLaunchKernelGGL(k, dim3(grid), dim3(64 * g.ws), g.lds, s,

@@ -59,14 +59,14 @@ inline FastGeom fast_geom(const XcGeom& g) {
 }
 
 // Largest workgroup (waves) of the specialised kernel for a precision form and channel
-// count.  The split forms' strips for 2..3 channels leave room for one workgroup per compute
+// count.  The split forms' strips for 2..4 channels leave room for one workgroup per compute
 // unit, so those kernels take 8 waves per reference block (two per SIMD); 4 otherwise.
-constexpr int fast_max_waves(int prec, int C) { return (prec != 0 && C >= 2 && C <= 3) ? 8 : 4; }
+constexpr int fast_max_waves(int prec, int C) { return (prec != 0 && C >= 2) ? 8 : 4; }
 
 // Kernel tier of the persistent batch launch for a precision form and channel count, and
 // the largest workgroup (waves) of each tier.
 constexpr int batch_tier(int prec, int C) {
-  return C == 4 ? 1 : (prec == 0 || C == 1 ? 0 : 2);
+  return prec == 0 ? (C == 4 ? 1 : 0) : (C == 1 ? 0 : 2);
 }
 constexpr int batch_max_waves(int tier) { return tier == 2 ? 8 : 4; }
 

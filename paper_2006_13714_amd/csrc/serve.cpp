@@ -4,9 +4,11 @@
 // sub-allocated per request (image, norm map, centring slot, outputs) and per step (batch
 // header), so admission never calls the device allocator.  Host memory: one pinned arena
 // holding each queued request's image, into which its results are copied back.
-// A step copies its requests' images in, runs the uneven-batch launch (one norm launch and
-// the persistent cross-term launches) and copies the results out, all on one of two
-// streams taken in turn, then records an event; consecutive steps overlap on the device.
+// A step copies its requests' images in on the input stream, runs the uneven-batch launch
+// (one norm launch and the persistent cross-term launches) on one of two compute streams
+// taken in turn, and copies the results out on the output stream, the three joined by
+// events.  Copies of one step therefore overlap the kernels of its neighbours, and the
+// kernels of consecutive steps overlap each other's tails.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,19 +43,19 @@ DevLayout dev_layout(const bm_desc& d) {
 }
 
 struct StepState {
-  hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
+  hipEvent_t in = nullptr, comp = nullptr, done = nullptr;
   bool recorded = false;
   bm_status status = BM_OK;
   ~StepState() {
-    if (done) (void)hipEventDestroy(done);
+    for (hipEvent_t e : {in, comp, done})
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
 class HipExecutor : public Executor {
  public:
   ~HipExecutor() override {
-    for (hipStream_t s : streams_)
+    for (hipStream_t s : {in_, comp_[0], comp_[1], out_})
       if (s) (void)hipStreamDestroy(s);
     if (dev_) (void)hipFree(dev_);
     if (host_) (void)hipHostFree(host_);
@@ -73,8 +75,8 @@ class HipExecutor : public Executor {
       host_ = nullptr;
       return fail(BM_ENOMEM, "server host arena hipHostMalloc(%lld)", (long long)host_bytes);
     }
-    for (hipStream_t& s : streams_)
-      if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+    for (hipStream_t* s : {&in_, &comp_[0], &comp_[1], &out_})
+      if ((e = hipStreamCreateWithFlags(s, hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(e, "hipStreamCreateWithFlags");
     return BM_OK;
   }
@@ -101,12 +103,13 @@ class HipExecutor : public Executor {
   bm_status begin_step(Step* s) override {
     auto ss = std::make_shared<StepState>();
     s->exec = ss;
-    ss->stream = streams_[next_++ % kStreams];
-    hipError_t e = hipEventCreateWithFlags(&ss->done, hipEventDisableTiming);
-    if (e != hipSuccess) {
-      ss->done = nullptr;
-      return hip_fail(e, "hipEventCreate");
-    }
+    hipError_t e;
+    for (hipEvent_t* ev : {&ss->in, &ss->comp, &ss->done})
+      if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) {
+        *ev = nullptr;
+        return hip_fail(e, "hipEventCreate");
+      }
+    hipStream_t comp = comp_[next_++ % 2];
     char* dbase = static_cast<char*>(dev_);
     char* hbase = static_cast<char*>(host_);
     std::vector<BatchEntry> ent(s->reqs.size());
@@ -114,27 +117,32 @@ class HipExecutor : public Executor {
       Request* r = s->reqs[i];
       const DevLayout L = dev_layout(r->desc);
       char* d = dbase + r->dev_off;
-      e = hipMemcpyAsync(d + L.img, hbase + r->host_off, r->img_bytes, hipMemcpyHostToDevice,
-                         ss->stream);
+      e = hipMemcpyAsync(d + L.img, hbase + r->host_off, r->img_bytes, hipMemcpyHostToDevice, in_);
       if (e != hipSuccess) return hip_fail(e, "request image copy");
       ent[i] = BatchEntry{static_cast<const bm_plan_s*>(r->exec.get()),
                           reinterpret_cast<const float*>(d + L.img),
                           reinterpret_cast<float*>(d + L.nrm), reinterpret_cast<float*>(d + L.ctr),
                           reinterpret_cast<int32_t*>(d + L.idx), reinterpret_cast<float*>(d + L.dist)};
     }
-    bm_status st = run_batch(ent.data(), (int)ent.size(), dbase + s->hdr_off, ss->stream);
+    if ((e = hipEventRecord(ss->in, in_)) != hipSuccess ||
+        (e = hipStreamWaitEvent(comp, ss->in, 0)) != hipSuccess)
+      return hip_fail(e, "input event");
+    bm_status st = run_batch(ent.data(), (int)ent.size(), dbase + s->hdr_off, comp);
     if (st != BM_OK) return st;
+    if ((e = hipEventRecord(ss->comp, comp)) != hipSuccess ||
+        (e = hipStreamWaitEvent(out_, ss->comp, 0)) != hipSuccess)
+      return hip_fail(e, "compute event");
     for (size_t i = 0; i < s->reqs.size(); ++i) {
       Request* r = s->reqs[i];
       const DevLayout L = dev_layout(r->desc);
       const int64_t n = r->n_ref * r->desc.k * 4;
       char* d = dbase + r->dev_off;
       char* h = hbase + r->host_off;
-      if ((e = hipMemcpyAsync(h, d + L.idx, n, hipMemcpyDeviceToHost, ss->stream)) != hipSuccess ||
-          (e = hipMemcpyAsync(h + n, d + L.dist, n, hipMemcpyDeviceToHost, ss->stream)) != hipSuccess)
+      if ((e = hipMemcpyAsync(h, d + L.idx, n, hipMemcpyDeviceToHost, out_)) != hipSuccess ||
+          (e = hipMemcpyAsync(h + n, d + L.dist, n, hipMemcpyDeviceToHost, out_)) != hipSuccess)
         return hip_fail(e, "result copy");
     }
-    if ((e = hipEventRecord(ss->done, ss->stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = hipEventRecord(ss->done, out_)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     ss->recorded = true;
     return BM_OK;
   }
@@ -150,9 +158,12 @@ class HipExecutor : public Executor {
 
   void wait_step(Step* s) override {
     auto* ss = static_cast<StepState*>(s->exec.get());
-    if (!ss) return;
-    if (ss->recorded) (void)hipEventSynchronize(ss->done);
-    else if (ss->stream) (void)hipStreamSynchronize(ss->stream);
+    if (ss && ss->recorded) {
+      (void)hipEventSynchronize(ss->done);
+      return;
+    }
+    // a step that failed while being enqueued: wait for whatever it did enqueue
+    for (hipStream_t st : {in_, comp_[0], comp_[1], out_}) (void)hipStreamSynchronize(st);
   }
 
   bm_status step_status(Step* s) override {
@@ -161,11 +172,11 @@ class HipExecutor : public Executor {
   }
 
  private:
-  static constexpr int kStreams = 2;
   int device_ = 0, max_lds_ = 0;
   void* dev_ = nullptr;
   void* host_ = nullptr;
-  hipStream_t streams_[kStreams] = {nullptr, nullptr};
+  hipStream_t in_ = nullptr, out_ = nullptr;
+  hipStream_t comp_[2] = {nullptr, nullptr};
   unsigned next_ = 0;
 };
 

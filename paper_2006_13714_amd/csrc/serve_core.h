@@ -12,6 +12,9 @@
 //      arena and fewer than max_inflight are admitted;
 //   3. launch the newly admitted requests as one step (copies in, one batch launch,
 //      copies out), without waiting for earlier steps: steps overlap on the device.
+// A step takes at most kMaxStep requests (and at most half of max_inflight), so that
+// under load several steps are in flight: slots freed by one step are refilled while the
+// others still run, and one step's copies overlap another's kernels.
 #pragma once
 
 #include <stdint.h>
@@ -141,6 +144,8 @@ inline int64_t desc_n_ref(const bm_desc& d) {
 
 class Scheduler {
  public:
+  static constexpr int64_t kMaxStep = 8;
+
   Scheduler(Executor* ex, const bm_server_cfg& cfg, int64_t dev_arena, int64_t host_arena)
       : ex_(ex), cfg_(cfg) {
     dev_.reset(dev_arena);
@@ -155,7 +160,8 @@ class Scheduler {
     return init_status_;
   }
 
-  // Validation of the descriptor is the caller's; this checks capacity and queues.
+  // Validation of the descriptor is the caller's; this checks capacity and queues.  The
+  // image is copied into the reserved host block outside the lock.
   bm_status submit(const bm_desc& d, const float* img, uint64_t* ticket, const char** why) {
     auto r = std::make_unique<Request>();
     r->desc = d;
@@ -163,14 +169,19 @@ class Scheduler {
     r->img_bytes = (int64_t)d.channels * d.height * d.width * 4;
     r->out_bytes = r->n_ref * d.k * 8;
     r->dev_bytes = ex_->request_bytes(d);
-    std::unique_lock<std::mutex> lk(mu_);
-    if (stop_) return *why = "server is shutting down", BM_EINVAL;
-    if (r->dev_bytes + ex_->step_header_bytes(1) > dev_.size())
-      return *why = "request alone exceeds the device budget", BM_EBUSY;
-    if ((int64_t)queue_.size() >= cfg_.max_queue) return *why = "queue full", BM_EBUSY;
-    if (!host_.alloc(std::max(r->img_bytes, r->out_bytes), &r->host_off))
-      return *why = "host staging memory full", BM_EBUSY;
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      if (stop_) return *why = "server is shutting down", BM_EINVAL;
+      if (r->dev_bytes + ex_->step_header_bytes(1) > dev_.size())
+        return *why = "request alone exceeds the device budget", BM_EBUSY;
+      if ((int64_t)(queue_.size() + copying_) >= cfg_.max_queue) return *why = "queue full", BM_EBUSY;
+      if (!host_.alloc(std::max(r->img_bytes, r->out_bytes), &r->host_off))
+        return *why = "host staging memory full", BM_EBUSY;
+      ++copying_;
+    }
     std::memcpy(static_cast<char*>(ex_->host_base()) + r->host_off, img, r->img_bytes);
+    std::unique_lock<std::mutex> lk(mu_);
+    --copying_;
     r->ticket = next_ticket_++;
     r->t_submit = now_s();
     *ticket = r->ticket;
@@ -180,12 +191,18 @@ class Scheduler {
     return BM_OK;
   }
 
+  // A finished request is retired under the lock and its results copied outside it.
   bm_status poll(uint64_t t, int32_t* idx, float* dist, bm_request_stats* st) {
-    std::unique_lock<std::mutex> lk(mu_);
-    auto it = reqs_.find(t);
-    if (it == reqs_.end()) return BM_ENOTFOUND;
-    Request* r = it->second.get();
-    if (r->state == ReqState::Queued || r->state == ReqState::Admitted) return BM_EAGAIN;
+    std::unique_ptr<Request> r;
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      auto it = reqs_.find(t);
+      if (it == reqs_.end()) return BM_ENOTFOUND;
+      if (it->second->state == ReqState::Queued || it->second->state == ReqState::Admitted)
+        return BM_EAGAIN;
+      r = std::move(it->second);
+      reqs_.erase(it);
+    }
     bm_status s = BM_OK;
     if (r->state == ReqState::Done) {
       const char* base = static_cast<const char*>(ex_->host_base()) + r->host_off;
@@ -201,8 +218,10 @@ class Scheduler {
     } else {
       s = r->state == ReqState::Cancelled ? BM_ECANCELED : r->status;
     }
-    if (r->host_off >= 0) host_.release(r->host_off);
-    reqs_.erase(it);
+    if (r->host_off >= 0) {
+      std::unique_lock<std::mutex> lk(mu_);
+      host_.release(r->host_off);
+    }
     return s;
   }
 
@@ -311,7 +330,9 @@ class Scheduler {
   // 2. admission (lock held): arrival order, stop at the first request that does not fit.
   //    The step header is reserved first, sized for the most requests this step can take.
   void admit(Step* step) {
-    const int64_t room = std::min<int64_t>((int64_t)queue_.size(), cfg_.max_inflight - admitted_);
+    const int64_t step_cap = std::max<int64_t>(1, std::min<int64_t>(kMaxStep, cfg_.max_inflight / 2));
+    const int64_t room = std::min<int64_t>(std::min<int64_t>((int64_t)queue_.size(), step_cap),
+                                           cfg_.max_inflight - admitted_);
     if (room <= 0) return;
     if (!dev_.alloc(ex_->step_header_bytes((int)room), &step->hdr_off)) return;
     std::vector<Request*> take;
@@ -386,6 +407,7 @@ class Scheduler {
   std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs_;
   uint64_t next_ticket_ = 1;
   int64_t admitted_ = 0;
+  int64_t copying_ = 0;  // submissions copying their image (counted against max_queue)
   bool stop_ = false, started_ = false;
   bm_status init_status_ = BM_OK;
   std::thread thread_;

@@ -10,9 +10,9 @@
 //
 // A kernel's register count and workgroup shape, and with them how many workgroups a
 // compute unit keeps, are shared by every body compiled into it.  The bodies are therefore
-// grouped in tiers of similar shape (batch_tier): float32 tier 0 holds 1..3 channels, the
-// split forms' tier 0 one channel and tier 2 two or three channels (8-wave blocks), and
-// tier 1 four channels.  A batch runs one persistent launch per tier present.
+// grouped in tiers of similar shape (batch_tier): float32 tier 0 holds 1..3 channels and
+// tier 1 four channels; the split forms' tier 0 holds one channel and tier 2 two to four
+// channels (8-wave blocks).  A batch runs one persistent launch per tier present.
 #pragma once
 
 #include "batch.h"
@@ -89,7 +89,9 @@ template <int PREC, int KR, int NT>
 static XcBatchKernel batch_tier_kernel(int tier) {
   switch (tier) {
     case 0: return xcorr_topk_batch<PREC, KR, NT, 0>;
-    case 1: return xcorr_topk_batch<PREC, KR, NT, 1>;
+    case 1:
+      if constexpr (PREC == 0) return xcorr_topk_batch<PREC, KR, NT, 1>;
+      break;
     case 2:
       if constexpr (PREC != 0) return xcorr_topk_batch<PREC, KR, NT, 2>;
       break;

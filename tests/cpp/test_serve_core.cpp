@@ -191,6 +191,7 @@ static void test_admission_by_footprint() {
   }
   CHECK(peak <= cfg.hbm_budget_bytes);
   CHECK(ex.max_step_ <= 2);
+  CHECK(s.max_step_size() <= Scheduler::kMaxStep);
   // a request larger than the whole budget is refused at once
   bm_desc big = desc(2048, 2048, 4);
   auto img = image(big, 1.f);
