@@ -54,7 +54,9 @@ typedef int32_t bm_status;
  * accumulate hi*hi + hi*lo + lo*hi in float32 on the matrix cores. */
 #define BM_PREC_FP32 0      /* float32 products, float32 accumulation                 */
 #define BM_PREC_BF16X3 1    /* bfloat16 hi/lo split, three products                   */
-#define BM_PREC_FP16X3 2    /* float16 hi/lo split after a power-of-two pre-scale     */
+#define BM_PREC_FP16X3 2    /* float16 hi/lo split after a power-of-two pre-scale,
+                               chosen per 4 x 4 block of references from the largest
+                               |x| around it (a property of the image, not of the call) */
 
 /* bm_desc.flags */
 #define BM_FLAG_CENTER 1u   /* subtract a per-channel mean before the cross term (the
@@ -92,7 +94,10 @@ bm_status bm_match(bm_plan_t plan, const float* d_img, int32_t* d_idx, float* d_
                    void* d_workspace, void* stream);
 
 /* Patch-norm map alone (the box filter, h_X (.) h_X of Sec. III-B): d_norm receives
- * (H-P+1)*(W-P+1) floats, row-major.  Asynchronous on `stream`. */
+ * (H-P+1)*(W-P+1) floats, row-major.  It also writes the plan's own workspace (centring
+ * constants, and the per-tile maxima of |x| that BM_PREC_FP16X3 reads), which the next
+ * bm_cross_topk on the same plan consumes: such pairs on one plan must not overlap in
+ * time.  Asynchronous on `stream`. */
 bm_status bm_norms(bm_plan_t plan, const float* d_img, float* d_norm, void* stream);
 
 /* Second step of bm_match on its own: the fused cross-term / distance / top-K kernel,
@@ -102,10 +107,18 @@ bm_status bm_norms(bm_plan_t plan, const float* d_img, float* d_norm, void* stre
 bm_status bm_cross_topk(bm_plan_t plan, const float* d_img, const float* d_norm,
                         int32_t* d_idx, float* d_dist, void* stream);
 
-/* Many images of uneven shapes in one persistent launch (plus one norm launch).  Entry b
- * uses plans[b], d_imgs[b], d_idx[b], d_dist[b].  d_workspace must hold
- * bm_batch_workspace() bytes or be NULL (then the library allocates and frees it inside
- * the call, which synchronises `stream`). */
+/* Many images of uneven shapes: one norm launch over all images, then one persistent
+ * launch per kernel tier present (a device counter hands out 4 x 4 reference blocks,
+ * costliest images first).  Tiers group block shapes that share registers and workgroup
+ * size: float32 images with 1..3 channels form one tier, 4 channels another; the split
+ * forms put 1 channel in one tier and 2..4 channels in another.  Images whose shape only
+ * the generic float32 kernel covers get a launch of their own.  Every image's results are
+ * bitwise those of bm_match with the same plan.  Entry b uses plans[b], d_imgs[b],
+ * d_idx[b], d_dist[b] (plans may repeat).  d_workspace must hold bm_batch_workspace()
+ * bytes or be NULL (then the library allocates and frees it inside the call, which
+ * synchronises `stream`); a workspace must not be reused before the call's work has
+ * finished on `stream`.  n = 0 is a no-op.  Errors: BM_EINVAL (NULL plan or pointer, plan
+ * from another device), BM_ENOTSUP, BM_ENOMEM, BM_EDEVICE. */
 bm_status bm_match_batch(int32_t n, const bm_plan_t* plans, const float* const* d_imgs,
                          int32_t* const* d_idx, float* const* d_dist, void* d_workspace,
                          void* stream);
@@ -145,24 +158,38 @@ typedef struct {
   int64_t n_ref;
 } bm_request_stats;
 
-/* Start a server on the current device with its own scheduler thread and streams. */
+/* Start a server on the current device: one device arena of hbm_budget_bytes (>= 1 MiB)
+ * sub-allocated per request (image, norm map, outputs) so that admission never calls the
+ * device allocator, a pinned host arena for queued images and returned results (the
+ * budget, clamped to [256 MiB, 8 GiB]), and a scheduler thread.  The scheduler admits
+ * queued requests in arrival order while their footprint fits the arena and fewer than
+ * max_inflight are admitted, launches newly admitted requests together as one step (at
+ * most 8, and at most max_inflight / 2), copies in on an input stream, runs the
+ * uneven-batch launch on one of two compute streams and copies results out on an output
+ * stream; steps overlap.  Requests are computed exactly as bm_match computes them.
+ * Errors: BM_EINVAL (cfg out of range), BM_ENOMEM, BM_EDEVICE. */
 bm_status bm_server_create(const bm_server_cfg* cfg, bm_server_t* out);
 
 /* Queue one request; the host image (C*H*W floats) is copied before the call returns.
- * BM_EBUSY when the queue is full or the request alone exceeds the device budget. */
+ * Thread-safe.  BM_EBUSY when max_queue requests wait, the host arena is full, or the
+ * request alone exceeds the device budget; BM_EINVAL / BM_ENOTSUP as bm_plan. */
 bm_status bm_submit(bm_server_t srv, const bm_desc* desc, const float* host_img,
                     uint64_t* ticket);
 
-/* Non-blocking.  BM_EAGAIN while pending; BM_OK once done: copies n_ref*K results into
- * the caller's host buffers (either may be NULL), fills stats (may be NULL) and retires
- * the ticket.  BM_ENOTFOUND for unknown or retired tickets, BM_ECANCELED if cancelled. */
+/* Non-blocking, thread-safe.  BM_EAGAIN while pending; BM_OK once done: copies n_ref*K
+ * results into the caller's host buffers (either may be NULL), fills stats (may be NULL)
+ * and retires the ticket.  BM_ENOTFOUND for unknown or retired tickets, BM_ECANCELED if
+ * cancelled; a request that failed returns its error (e.g. BM_ENOTSUP, BM_EDEVICE) and is
+ * retired. */
 bm_status bm_poll(bm_server_t srv, uint64_t ticket, int32_t* host_idx, float* host_dist,
                   bm_request_stats* stats);
 
-/* Cancel a queued ticket (admitted work finishes and is discarded). */
+/* Cancel a ticket: a queued request is dropped at once; an admitted one finishes on the
+ * device and its results are discarded.  Either way bm_poll then returns BM_ECANCELED. */
 bm_status bm_cancel(bm_server_t srv, uint64_t ticket);
 
-/* Drain admitted work, stop the scheduler, free everything. */
+/* Stop accepting, wait for admitted work to finish, drop queued requests, stop the
+ * scheduler and free both arenas; every ticket of the server becomes invalid. */
 bm_status bm_server_destroy(bm_server_t srv);
 
 const char* bm_status_str(bm_status s);

@@ -208,14 +208,14 @@ bm_status bm_plan_destroy(bm_plan_t plan) {
 bm_status bm_norms(bm_plan_t plan, const float* d_img, float* d_norm, void* stream) {
   if (!plan) return fail(BM_EINVAL, "plan is NULL");
   if (!d_img || !d_norm) return fail(BM_EINVAL, "NULL device pointer");
-  return run_norms(*plan, d_img, d_norm, plan_centers(*plan, plan->ws), (hipStream_t)stream);
+  return run_norms(*plan, d_img, d_norm, plan_aux(*plan, plan->ws), (hipStream_t)stream);
 }
 
 bm_status bm_cross_topk(bm_plan_t plan, const float* d_img, const float* d_norm,
                         int32_t* d_idx, float* d_dist, void* stream) {
   if (!plan) return fail(BM_EINVAL, "plan is NULL");
   if (!d_img || !d_norm || !d_idx || !d_dist) return fail(BM_EINVAL, "NULL device pointer");
-  return run_cross_topk(*plan, d_img, d_norm, plan_centers(*plan, plan->ws), d_idx, d_dist,
+  return run_cross_topk(*plan, d_img, d_norm, plan_aux(*plan, plan->ws), d_idx, d_dist,
                         (hipStream_t)stream);
 }
 

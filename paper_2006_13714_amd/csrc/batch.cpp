@@ -159,8 +159,10 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
     if (x.plan->device != dev)
       return fail(BM_EINVAL, "batch entry %d: plan made on device %d, current is %d", b,
                   x.plan->device, dev);
-    if (plan_needs_centers(*x.plan) && !x.centers)
+    if (plan_needs_centers(*x.plan) && !x.aux.centers)
       return fail(BM_EINVAL, "batch entry %d: centring plan without a centres slot", b);
+    if (x.plan->desc.precision == BM_PREC_FP16X3 && !x.aux.amax)
+      return fail(BM_EINVAL, "batch entry %d: float16 plan without a max map slot", b);
   }
 
   // ---- groups of the persistent kernel; the rest run the generic kernel one by one
@@ -228,7 +230,8 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
       BatchXc& r = hx[rec++];
       r.img = e[b].img;
       r.nrm = e[b].nrm;
-      r.centers = plan_needs_centers(p) ? e[b].centers : nullptr;
+      r.centers = e[b].aux.centers;
+      r.amax = e[b].aux.amax;
       r.idx = e[b].idx;
       r.dist = e[b].dist;
       r.cls = shape_class(p.desc);
@@ -243,7 +246,8 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
     BatchNorm& r = hn[b];
     r.img = e[b].img;
     r.out = e[b].nrm;
-    r.centers = plan_needs_centers(p) ? e[b].centers : nullptr;
+    r.centers = e[b].aux.centers;
+    r.amax = e[b].aux.amax;
     r.g = NormGeom{p.geom.H, p.geom.W, p.geom.C, p.geom.P, p.geom.Hv, p.geom.Wv};
     int tx, ty;
     norm_tiles(r.g, &tx, &ty);
@@ -260,8 +264,8 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
   // ---- launches: centring constants, all norms, persistent groups, generic images
   for (int b = 0; b < n; ++b) {
     const bm_plan_s& p = *e[b].plan;
-    if (!plan_needs_centers(p)) continue;
-    he = launch_centers(e[b].img, p.geom.C, p.geom.H, p.geom.W, e[b].centers, s);
+    if (!e[b].aux.centers) continue;
+    he = launch_centers(e[b].img, p.geom.C, p.geom.H, p.geom.W, e[b].aux.centers, s);
     if (he != hipSuccess) return hip_fail(he, "centring launch");
   }
   unsigned* counters = reinterpret_cast<unsigned*>(dh);
@@ -287,21 +291,20 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
     ++q;
   }
   for (int b : generic) {
-    bm_status st = run_cross_topk(*e[b].plan, e[b].img, e[b].nrm,
-                                  plan_needs_centers(*e[b].plan) ? e[b].centers : nullptr,
-                                  e[b].idx, e[b].dist, s);
+    bm_status st = run_cross_topk(*e[b].plan, e[b].img, e[b].nrm, e[b].aux, e[b].idx,
+                                  e[b].dist, s);
     if (st != BM_OK) return st;
   }
   return BM_OK;
 }
 
-// bm_match_batch workspace: [header: counters + records] then per image
-// [norm map][centring constants]
+// bm_match_batch workspace: [header: counters + records] then per image a plan workspace
+// layout [norm map][auxiliary slots]
 static int64_t batch_ws_layout(int n, const bm_plan_t* plans, std::vector<int64_t>* offs) {
   int64_t off = batch_header_bytes(n);
   for (int b = 0; b < n; ++b) {
     if (offs) offs->push_back(off);
-    off += align256((int64_t)plans[b]->geom.Hv * plans[b]->geom.Wv * 4) + 256;
+    off += desc_workspace_bytes(plans[b]->desc);
   }
   return off;
 }
@@ -345,11 +348,10 @@ bm_status bm_match_batch(int32_t n, const bm_plan_t* plans, const float* const* 
   std::vector<BatchEntry> ent(n);
   unsigned char* base = static_cast<unsigned char*>(ws);
   for (int b = 0; b < n; ++b) {
-    const XcGeom& g = plans[b]->geom;
     ent[b].plan = plans[b];
     ent[b].img = d_imgs[b];
     ent[b].nrm = reinterpret_cast<float*>(base + offs[b]);
-    ent[b].centers = reinterpret_cast<float*>(base + offs[b] + align256((int64_t)g.Hv * g.Wv * 4));
+    ent[b].aux = plan_aux(*plans[b], base + offs[b]);
     ent[b].idx = d_idx[b];
     ent[b].dist = d_dist[b];
   }

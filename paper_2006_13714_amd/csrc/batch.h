@@ -15,6 +15,7 @@ struct BatchNorm {
   const float* img;
   float* out;
   const float* centers;  // per-channel centring constants or null
+  float* amax;           // per-tile max |x - centre| map or null
   NormGeom g;
   int tile_begin, tiles_x;
 };
@@ -25,6 +26,7 @@ struct BatchXc {
   const float* img;
   const float* nrm;
   const float* centers;
+  const float* amax;
   int* idx;
   float* dist;
   int cls;         // shape class: (C - 1) * 3 + (ceil(P / 2) - 2)

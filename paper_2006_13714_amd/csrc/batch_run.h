@@ -7,13 +7,13 @@
 
 namespace bmk {
 
-// One image of a batch: its plan, image, norm map and centring slot (device memory the
-// caller owns; `centers` may be null unless the plan centres) and outputs.
+// One image of a batch: its plan, image, norm map and the norm pass's auxiliary slots
+// (device memory the caller owns; see aux_at) and outputs.
 struct BatchEntry {
   const bm_plan_s* plan;
   const float* img;
   float* nrm;
-  float* centers;
+  NormAux aux;
   int32_t* idx;
   float* dist;
 };

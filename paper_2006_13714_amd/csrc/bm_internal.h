@@ -15,6 +15,12 @@ constexpr int kTileN = 16;        // candidates per matrix tile (one row segment
 constexpr int kFastRS = 80;       // LDS row stride (words) of the specialised float32 kernel
 constexpr int kSplitRW = 64;      // LDS row stride (words) of the specialised split kernels
 
+// Output tile of the norm pass.  Tile (tx, ty) stages the input window rows
+// [16 ty, 16 ty + 16 + P - 1) x columns [64 tx, 64 tx + 64 + P - 1), clipped to the image,
+// so every pixel lies in the tile (min(x / 64, ntx - 1), min(y / 16, nty - 1)).
+constexpr int kNormTX = 64;
+constexpr int kNormTY = 16;
+
 // Geometry of one fused cross-term / distance / top-K launch.  All sizes in elements.
 struct XcGeom {
   int H, W, C, P, Pe, s, r, K;
@@ -46,6 +52,7 @@ struct FastGeom {
   int nry, nrx, nwg_x, nwg_total;
   int SH, SW, NH, CAP, p1_step;
   int lds_strip_off, lds_norm_off, lds_buf_off;
+  int ntx, nty;  // tile grid of the norm pass (its per-tile max |x| map)
 };
 
 inline FastGeom fast_geom(const XcGeom& g) {
@@ -55,13 +62,20 @@ inline FastGeom fast_geom(const XcGeom& g) {
   f.SH = g.SH; f.SW = g.SW; f.NH = g.NH; f.CAP = g.CAP; f.p1_step = g.p1_step;
   f.lds_strip_off = g.lds_strip_off; f.lds_norm_off = g.lds_norm_off;
   f.lds_buf_off = g.lds_buf_off;
+  f.ntx = (g.Wv + kNormTX - 1) / kNormTX;
+  f.nty = (g.Hv + kNormTY - 1) / kNormTY;
   return f;
 }
 
 // Largest workgroup (waves) of the specialised kernel for a precision form and channel
-// count.  The split forms' strips for 2..4 channels leave room for one workgroup per compute
-// unit, so those kernels take 8 waves per reference block (two per SIMD); 4 otherwise.
-constexpr int fast_max_waves(int prec, int C) { return (prec != 0 && C >= 2) ? 8 : 4; }
+// count: 8 waves per reference block, except the 4-channel float32 bodies, whose registers
+// leave room for one wave per SIMD only.
+constexpr int fast_max_waves(int prec, int C) { return (prec == 0 && C == 4) ? 4 : 8; }
+
+// Waves per reference block the built-in rule starts from: the split forms' strips for
+// 2..4 channels leave room for one workgroup per compute unit, which then needs 8 waves to
+// keep two per SIMD; the other classes keep several 4-wave workgroups per compute unit.
+constexpr int fast_default_waves(int prec, int C) { return (prec != 0 && C >= 2) ? 8 : 4; }
 
 // Kernel tier of the persistent batch launch for a precision form and channel count, and
 // the largest workgroup (waves) of each tier.
@@ -72,6 +86,14 @@ constexpr int batch_max_waves(int tier) { return tier == 2 ? 8 : 4; }
 
 struct NormGeom {
   int H, W, C, P, Hv, Wv;
+};
+
+// Per-image outputs of the norm pass that the cross-term pass reads besides the norm map:
+// the centring constants (null unless centring) and the per-tile max |x - centre| map
+// (null unless the float16 split form, which derives its pre-scale from it).
+struct NormAux {
+  float* centers;
+  float* amax;
 };
 
 }  // namespace bmk

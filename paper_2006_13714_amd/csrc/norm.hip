@@ -11,6 +11,9 @@
 // float64, so every output is the float32 rounding of the exact norm.  HBM-bound: each
 // input element is read once from HBM and each output written once.
 //
+// Each tile also writes max |x - center_c| over its staged window (all channels) to a
+// per-tile map when asked; the float16 split form takes its per-block pre-scale from it.
+//
 // The batch form covers many images in one launch: workgroup b finds its image by a
 // binary search over the images' first tile numbers.
 #include <hip/hip_runtime.h>
@@ -20,18 +23,17 @@
 
 namespace bmk {
 
-constexpr int kNormTX = 64;
-constexpr int kNormTY = 16;
 constexpr int kMaxP = 16;
 
 struct NormLds {
   float tile[kNormTY + kMaxP - 1][kNormTX + kMaxP];
   double hs[kNormTY + kMaxP - 1][kNormTX];
+  float red[4];
 };
 
 __device__ __forceinline__ void norm_tile(const float* __restrict__ img, float* __restrict__ out,
                                           const NormGeom& g, const float* __restrict__ centers,
-                                          int bx, int by, NormLds& sh) {
+                                          float* __restrict__ amax, int bx, int by, NormLds& sh) {
   const int tx = threadIdx.x & 63;
   const int ty = threadIdx.x >> 6;  // 0..3
   const int ox0 = bx * kNormTX;
@@ -39,6 +41,7 @@ __device__ __forceinline__ void norm_tile(const float* __restrict__ img, float* 
   const int rows = kNormTY + g.P - 1;
   const int cols = kNormTX + g.P - 1;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  float vmax = 0.f;
 
   for (int c = 0; c < g.C; ++c) {
     const float* plane = img + (size_t)c * g.H * g.W;
@@ -50,6 +53,7 @@ __device__ __forceinline__ void norm_tile(const float* __restrict__ img, float* 
         float v = 0.f;
         if (y < g.H && x < g.W) v = plane[(size_t)y * g.W + x] - cc;
         sh.tile[rr][xx] = v;
+        vmax = fmaxf(vmax, fabsf(v));
       }
     }
     __syncthreads();
@@ -77,13 +81,23 @@ __device__ __forceinline__ void norm_tile(const float* __restrict__ img, float* 
     const int ox = ox0 + tx;
     if (oy < g.Hv && ox < g.Wv) out[(size_t)oy * g.Wv + ox] = (float)acc[k];
   }
+  if (amax) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
+    if (tx == 0) sh.red[ty] = vmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int ntx = (g.Wv + kNormTX - 1) / kNormTX;
+      amax[by * ntx + bx] = fmaxf(fmaxf(sh.red[0], sh.red[1]), fmaxf(sh.red[2], sh.red[3]));
+    }
+  }
 }
 
 __global__ void __launch_bounds__(256)
 norm_box_kernel(const float* __restrict__ img, float* __restrict__ out, NormGeom g,
-                const float* __restrict__ centers) {
+                const float* __restrict__ centers, float* __restrict__ amax) {
   __shared__ NormLds sh;
-  norm_tile(img, out, g, centers, blockIdx.x, blockIdx.y, sh);
+  norm_tile(img, out, g, centers, amax, blockIdx.x, blockIdx.y, sh);
 }
 
 __global__ void __launch_bounds__(256)
@@ -102,7 +116,7 @@ norm_box_batch_kernel(const BatchNorm* __restrict__ items, int n, unsigned* __re
   const BatchNorm it = load_uniform(&items[lo]);
   const int t = b - it.tile_begin;
   const int ty = t / it.tiles_x;
-  norm_tile(it.img, it.out, it.g, it.centers, t - ty * it.tiles_x, ty, sh);
+  norm_tile(it.img, it.out, it.g, it.centers, it.amax, t - ty * it.tiles_x, ty, sh);
 }
 
 void norm_tiles(const NormGeom& g, int* tiles_x, int* tiles_y) {
@@ -111,10 +125,11 @@ void norm_tiles(const NormGeom& g, int* tiles_x, int* tiles_y) {
 }
 
 hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* centers,
-                       hipStream_t stream) {
+                       float* amax, hipStream_t stream) {
   int tx, ty;
   norm_tiles(g, &tx, &ty);
-  hipLaunchKernelGGL(norm_box_kernel, dim3(tx, ty), dim3(256), 0, stream, img, out, g, centers);
+  hipLaunchKernelGGL(norm_box_kernel, dim3(tx, ty), dim3(256), 0, stream, img, out, g, centers,
+                     amax);
   return hipGetLastError();
 }
 

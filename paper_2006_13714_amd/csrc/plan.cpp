@@ -11,7 +11,7 @@
 namespace bmk {
 
 hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const float* centers,
-                       hipStream_t stream);
+                       float* amax, hipStream_t stream);
 hipError_t launch_centers(const float* img, int C, int H, int W, float* centers,
                           hipStream_t stream);
 hipError_t launch_xcorr_f32(int ks_bucket, int kr, const float* img, const float* nrm,
@@ -21,8 +21,8 @@ int f32_step_bucket(int ks);
 hipError_t prepare_xcorr_f32(int ks_bucket, int kr, int lds_bytes);
 hipError_t prepare_xcorr_fast(int prec, int c, int h2, int kr, int nt, int lds_bytes);
 hipError_t launch_xcorr_fast(int prec, int c, int h2, int kr, int nt, const float* img,
-                             const float* nrm, const float* centers, int* idx, float* dist,
-                             const XcGeom& g, hipStream_t stream);
+                             const float* nrm, const float* centers, const float* amax,
+                             int* idx, float* dist, const XcGeom& g, hipStream_t stream);
 
 static int kr_for(int k) { return k <= 16 ? 1 : (k <= 32 ? 2 : 4); }
 
@@ -63,18 +63,34 @@ void format_cfg(const TileCfg& c, char* out, int len) {
   else snprintf(out, len, "generic wy=%d wx=%d cap=%d", c.wy, c.wx, c.cap);
 }
 
-// workspace: [norm map (Hv*Wv floats)] [centring constants: 8 floats] (256-byte aligned)
-int64_t plan_workspace_bytes(const bm_plan_s& p) {
-  const XcGeom& g = p.geom;
-  return align256((int64_t)g.Hv * g.Wv * 4) + 256;
+// workspace: [norm map (Hv*Wv floats)] [centring constants: 8 floats] [per-tile max map of
+// the norm pass] (256-byte aligned parts)
+int64_t norm_tile_count(const bm_desc& d) {
+  const int64_t hv = d.height - d.patch + 1, wv = d.width - d.patch + 1;
+  return ((wv + kNormTX - 1) / kNormTX) * ((hv + kNormTY - 1) / kNormTY);
 }
+
+int64_t desc_workspace_bytes(const bm_desc& d) {
+  const int64_t hv = d.height - d.patch + 1, wv = d.width - d.patch + 1;
+  return align256(hv * wv * 4) + 256 + align256(norm_tile_count(d) * 4);
+}
+
+int64_t plan_workspace_bytes(const bm_plan_s& p) { return desc_workspace_bytes(p.desc); }
 
 bool plan_needs_centers(const bm_plan_s& p) { return (p.desc.flags & BM_FLAG_CENTER) != 0; }
 
-float* plan_centers(const bm_plan_s& p, void* ws) {
-  if (!plan_needs_centers(p) || !ws) return nullptr;
-  return reinterpret_cast<float*>(static_cast<char*>(ws) +
-                                  align256((int64_t)p.geom.Hv * p.geom.Wv * 4));
+NormAux aux_at(const bm_plan_s& p, void* slot) {
+  NormAux a{nullptr, nullptr};
+  if (!slot) return a;
+  char* base = static_cast<char*>(slot);
+  if (plan_needs_centers(p)) a.centers = reinterpret_cast<float*>(base);
+  if (p.desc.precision == BM_PREC_FP16X3) a.amax = reinterpret_cast<float*>(base + 256);
+  return a;
+}
+
+NormAux plan_aux(const bm_plan_s& p, void* ws) {
+  if (!ws) return NormAux{nullptr, nullptr};
+  return aux_at(p, static_cast<char*>(ws) + align256((int64_t)p.geom.Hv * p.geom.Wv * 4));
 }
 
 bool fast_eligible(const bm_desc& d) {
@@ -120,17 +136,21 @@ bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_
 // least two workgroups, else the configuration with the most workgroups that fits.
 static bm_status builtin_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
   if (fast_eligible(d)) {
+    // 8-wave blocks take a 48-entry candidate buffer where it fits (fewer flushes)
     for (int ws : {8, 4, 2, 1}) {
-      if (ws > fast_max_waves(d.precision, d.channels)) continue;
-      XcGeom g;
-      fill_geom(d, ws, 1, 32, true, g);
-      if (g.lds_bytes <= max_lds && g.SW <= g.RS) {
-        TileCfg c;
-        c.fast = true;
-        c.wy = ws;
-        c.cap = 32;
-        c.p1 = 2;
-        return apply_config(d, c, max_lds, p);
+      if (ws > fast_default_waves(d.precision, d.channels)) continue;
+      for (int cap : {48, 32}) {
+        if (cap == 48 && ws != 8) continue;
+        XcGeom g;
+        fill_geom(d, ws, 1, cap, true, g);
+        if (g.lds_bytes <= max_lds && g.SW <= g.RS) {
+          TileCfg c;
+          c.fast = true;
+          c.wy = ws;
+          c.cap = cap;
+          c.p1 = 2;
+          return apply_config(d, c, max_lds, p);
+        }
       }
     }
   }
@@ -181,28 +201,32 @@ bm_status choose_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
   return builtin_config(d, max_lds, p);
 }
 
-bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, float* centers,
+bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, const NormAux& aux,
                     hipStream_t s) {
   const XcGeom& g = p.geom;
   hipError_t e;
-  if (centers) {
-    e = launch_centers(d_img, g.C, g.H, g.W, centers, s);
+  if (plan_needs_centers(p) && !aux.centers) return fail(BM_EINVAL, "no centring slot");
+  if (p.desc.precision == BM_PREC_FP16X3 && !aux.amax) return fail(BM_EINVAL, "no max map slot");
+  if (aux.centers) {
+    e = launch_centers(d_img, g.C, g.H, g.W, aux.centers, s);
     if (e != hipSuccess) return hip_fail(e, "centring launch");
   }
   NormGeom ng{g.H, g.W, g.C, g.P, g.Hv, g.Wv};
-  e = launch_norm(d_img, d_norm, ng, centers, s);
+  e = launch_norm(d_img, d_norm, ng, aux.centers, aux.amax, s);
   if (e != hipSuccess) return hip_fail(e, "norm launch");
   return BM_OK;
 }
 
 bm_status run_cross_topk(const bm_plan_s& p, const float* d_img, const float* d_norm,
-                         const float* centers, int32_t* d_idx, float* d_dist, hipStream_t s) {
+                         const NormAux& aux, int32_t* d_idx, float* d_dist, hipStream_t s) {
   const bm_desc& d = p.desc;
+  if (d.precision == BM_PREC_FP16X3 && !aux.amax) return fail(BM_EINVAL, "no max map slot");
   hipError_t e = p.geom.fast
                      ? launch_xcorr_fast(d.precision, d.channels, (d.patch + 1) / 2, p.kr,
-                                         p.geom.NT, d_img, d_norm, centers, d_idx, d_dist, p.geom, s)
-                     : launch_xcorr_f32(p.ks_bucket, p.kr, d_img, d_norm, centers, d_idx, d_dist,
-                                        p.geom, s);
+                                         p.geom.NT, d_img, d_norm, aux.centers, aux.amax, d_idx,
+                                         d_dist, p.geom, s)
+                     : launch_xcorr_f32(p.ks_bucket, p.kr, d_img, d_norm, aux.centers, d_idx,
+                                        d_dist, p.geom, s);
   if (e != hipSuccess) return hip_fail(e, "cross-term launch");
   return BM_OK;
 }
@@ -211,10 +235,10 @@ bm_status run_match(const bm_plan_s& p, const float* d_img, int32_t* d_idx, floa
                     void* ws, hipStream_t s) {
   if (!ws) return fail(BM_EINVAL, "no workspace");
   float* nrm = static_cast<float*>(ws);
-  float* centers = plan_centers(p, ws);
-  bm_status st = run_norms(p, d_img, nrm, centers, s);
+  const NormAux aux = plan_aux(p, ws);
+  bm_status st = run_norms(p, d_img, nrm, aux, s);
   if (st != BM_OK) return st;
-  return run_cross_topk(p, d_img, nrm, centers, d_idx, d_dist, s);
+  return run_cross_topk(p, d_img, nrm, aux, d_idx, d_dist, s);
 }
 
 }  // namespace bmk

@@ -46,14 +46,20 @@ bool fast_eligible(const bm_desc& d);
 bm_status choose_config(const bm_desc& d, int max_lds, bm_plan_s* p);
 bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_s* p);
 int64_t plan_workspace_bytes(const bm_plan_s& p);
-// centring constants slot inside a workspace, or NULL if the plan does not centre
+// Workspace of a descriptor (norm map, centring slot, per-tile max map); the auxiliary
+// slots sit in a region of 256 + align256(norm_tile_count * 4) bytes after the norm map.
+int64_t norm_tile_count(const bm_desc& d);
+int64_t desc_workspace_bytes(const bm_desc& d);
 bool plan_needs_centers(const bm_plan_s& p);
-float* plan_centers(const bm_plan_s& p, void* ws);
-// norms (and, when the plan centres, the centring constants first into `centers`)
-bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, float* centers,
+// auxiliary outputs of the norm pass inside an auxiliary region (aux_at) or a plan
+// workspace (plan_aux); unused slots are null
+NormAux aux_at(const bm_plan_s& p, void* slot);
+NormAux plan_aux(const bm_plan_s& p, void* ws);
+// norms (and, when the plan centres, the centring constants first)
+bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, const NormAux& aux,
                     hipStream_t s);
 bm_status run_cross_topk(const bm_plan_s& p, const float* d_img, const float* d_norm,
-                         const float* centers, int32_t* d_idx, float* d_dist, hipStream_t s);
+                         const NormAux& aux, int32_t* d_idx, float* d_dist, hipStream_t s);
 bm_status run_match(const bm_plan_s& p, const float* d_img, int32_t* d_idx, float* d_dist,
                     void* ws, hipStream_t s);
 

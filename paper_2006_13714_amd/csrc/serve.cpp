@@ -25,8 +25,9 @@ namespace {
 
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
+// request memory: [image][plan workspace layout: norm map, auxiliary slots][idx][dist]
 struct DevLayout {
-  int64_t img, nrm, ctr, idx, dist, total;
+  int64_t img, nrm, aux, idx, dist, total;
 };
 
 DevLayout dev_layout(const bm_desc& d) {
@@ -35,8 +36,8 @@ DevLayout dev_layout(const bm_desc& d) {
   const int64_t out = desc_n_ref(d) * d.k * 4;
   L.img = 0;
   L.nrm = L.img + align256((int64_t)d.channels * d.height * d.width * 4);
-  L.ctr = L.nrm + align256(hv * wv * 4);
-  L.idx = L.ctr + 256;
+  L.aux = L.nrm + align256(hv * wv * 4);
+  L.idx = L.nrm + desc_workspace_bytes(d);
   L.dist = L.idx + align256(out);
   L.total = L.dist + align256(out);
   return L;
@@ -119,9 +120,9 @@ class HipExecutor : public Executor {
       char* d = dbase + r->dev_off;
       e = hipMemcpyAsync(d + L.img, hbase + r->host_off, r->img_bytes, hipMemcpyHostToDevice, in_);
       if (e != hipSuccess) return hip_fail(e, "request image copy");
-      ent[i] = BatchEntry{static_cast<const bm_plan_s*>(r->exec.get()),
-                          reinterpret_cast<const float*>(d + L.img),
-                          reinterpret_cast<float*>(d + L.nrm), reinterpret_cast<float*>(d + L.ctr),
+      const bm_plan_s* plan = static_cast<const bm_plan_s*>(r->exec.get());
+      ent[i] = BatchEntry{plan, reinterpret_cast<const float*>(d + L.img),
+                          reinterpret_cast<float*>(d + L.nrm), aux_at(*plan, d + L.aux),
                           reinterpret_cast<int32_t*>(d + L.idx), reinterpret_cast<float*>(d + L.dist)};
     }
     if ((e = hipEventRecord(ss->in, in_)) != hipSuccess ||

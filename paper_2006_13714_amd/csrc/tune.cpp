@@ -101,7 +101,7 @@ static std::vector<TileCfg> candidates(const bm_desc& d) {
   if (fast_eligible(d)) {
     for (int ws : {1, 2, 4, 8})
       for (int p1 : {1, 2, 3, 4})
-        for (int cap : {32, 64}) {
+        for (int cap : {32, 48, 64}) {
           if (ws > fast_max_waves(d.precision, d.channels)) continue;
           TileCfg c;
           c.fast = true;
@@ -144,10 +144,8 @@ bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, cha
   const int64_t n_ref = (int64_t)((d.height - d.patch) / d.stride + 1) *
                         ((d.width - d.patch) / d.stride + 1);
   const int64_t img_elems = (int64_t)d.channels * d.height * d.width;
-  const int64_t norm_elems = (int64_t)(d.height - d.patch + 1) * (d.width - d.patch + 1);
   float* own_img = nullptr;
-  float* nrm = nullptr;
-  float* stats = nullptr;
+  float* nrm = nullptr;  // a plan workspace: norm map, then the auxiliary slots
   int32_t* idx = nullptr;
   float* dist = nullptr;
   hipStream_t s = nullptr;
@@ -156,7 +154,6 @@ bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, cha
   float best_ms = 1e30f;
   auto cleanup = [&]() {
     if (own_img) (void)hipFree(own_img);
-    if (stats) (void)hipFree(stats);
     if (nrm) (void)hipFree(nrm);
     if (idx) (void)hipFree(idx);
     if (dist) (void)hipFree(dist);
@@ -164,7 +161,7 @@ bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, cha
     if (e1) (void)hipEventDestroy(e1);
     if (s) (void)hipStreamDestroy(s);
   };
-  if (hipMalloc(&nrm, norm_elems * 4) != hipSuccess || hipMalloc(&stats, 256) != hipSuccess ||
+  if (hipMalloc(&nrm, desc_workspace_bytes(d)) != hipSuccess ||
       hipMalloc(&idx, n_ref * d.k * 4) != hipSuccess ||
       hipMalloc(&dist, n_ref * d.k * 4) != hipSuccess) {
     cleanup();
@@ -192,13 +189,13 @@ bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, cha
     p.desc = d;
     p.device = dev;
     if (apply_config(d, c, max_lds, &p) != BM_OK) continue;
-    if (run_norms(p, img, nrm, plan_needs_centers(p) ? stats : nullptr, s) != BM_OK) continue;
-    const float* st = plan_needs_centers(p) ? stats : nullptr;
-    bool ok = run_cross_topk(p, img, nrm, st, idx, dist, s) == BM_OK;
+    const NormAux aux = plan_aux(p, nrm);
+    if (run_norms(p, img, nrm, aux, s) != BM_OK) continue;
+    bool ok = run_cross_topk(p, img, nrm, aux, idx, dist, s) == BM_OK;
     if (!ok) continue;
     (void)hipEventRecord(e0, s);
     for (int i = 0; i < reps && ok; ++i)
-      ok = run_cross_topk(p, img, nrm, st, idx, dist, s) == BM_OK;
+      ok = run_cross_topk(p, img, nrm, aux, idx, dist, s) == BM_OK;
     (void)hipEventRecord(e1, s);
     if (!ok || hipEventSynchronize(e1) != hipSuccess) continue;
     float ms = 0.f;

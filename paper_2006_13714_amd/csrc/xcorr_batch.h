@@ -26,8 +26,8 @@ __device__ __forceinline__ void batch_block(const BatchXc& r, int blk, unsigned 
     // split forms need patch sides 5..8; the host never forms such items
     (void)r, (void)blk, (void)lds;
   } else {
-    fast_block<CtFor<PREC, C, H2>, C, KR, NT>(r.img, r.nrm, r.centers, r.idx, r.dist, r.g, blk,
-                                              lds);
+    fast_block<CtFor<PREC, C, H2>, C, KR, NT>(r.img, r.nrm, r.centers, r.amax, r.idx, r.dist,
+                                              r.g, blk, lds);
   }
 }
 

@@ -41,34 +41,28 @@
 
 namespace bmk {
 
-// max |x - centre| over the in-image pixels of the strip rows first, first + step, ...
-// (this thread's share; rows are image rows x channels as in the policies' staging)
-template <int C>
-__device__ __forceinline__ float strip_absmax(const float* __restrict__ img, const FastGeom& g,
-                                              int SY0, int SX0, int first, int step, int lane,
-                                              const float* center) {
+// Upper bound of max |x - centre| over the strip rows [y0, y1] x columns [x0, x1] (image
+// coordinates, already clipped): the largest entry of the norm pass's per-tile map over
+// the tiles that hold those pixels.  Wave-uniform.
+__device__ __forceinline__ float strip_absmax(const float* __restrict__ amax, const FastGeom& g,
+                                              int y0, int y1, int x0, int x1) {
+  const int ty0 = min(y0 / kNormTY, g.nty - 1), ty1 = min(y1 / kNormTY, g.nty - 1);
+  const int tx0 = min(x0 / kNormTX, g.ntx - 1), tx1 = min(x1 / kNormTX, g.ntx - 1);
   float m = 0.f;
-  for (int row = first; row < g.SH * C; row += step) {
-    const int y = row / C;
-    const int c = row - y * C;
-    const int iy = SY0 + y;
-    if ((iy < 0) | (iy >= g.H)) continue;
-    const float* src = img + ((size_t)c * g.H + iy) * g.W;
-    for (int x = lane; x < g.SW; x += 64) {
-      const int ix = SX0 + x;
-      if ((ix >= 0) & (ix < g.W)) m = fmaxf(m, fabsf(src[ix] - center[c]));
-    }
-  }
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx) m = fmaxf(m, amax[ty * g.ntx + tx]);
   return m;
 }
 
 // One 4 x 4 reference block `blk` (row-major over the block grid) of one image, computed by
 // the whole workgroup (blockDim.x / 64 waves).  `centers` holds the per-channel centring
-// constants or is null.  Every thread of the workgroup must call it (it synchronises).
+// constants or is null; `amax` is the norm pass's per-tile max map (float16 form only).
+// Every thread of the workgroup must call it (it synchronises).
 template <class CT, int C, int KR, int NT>
 __device__ __forceinline__ void fast_block(const float* __restrict__ img,
                                            const float* __restrict__ nrm,
                                            const float* __restrict__ centers,
+                                           const float* __restrict__ amax,
                                            int* __restrict__ out_idx,
                                            float* __restrict__ out_dist, const FastGeom& g,
                                            int blk, unsigned char* lds) {
@@ -103,14 +97,8 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
 #pragma unroll
   for (int c = 0; c < 8; ++c) center[c] = (centers && c < C) ? centers[c] : 0.f;
   if constexpr (CT::kScaled) {
-    float m = strip_absmax<C>(img, g, SY0, SX0, wave, S, lane, center);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    float* red = reinterpret_cast<float*>(buf_all);
-    if (lane == 0) red[wave] = m;
-    __syncthreads();
-    m = red[0];
-    for (int w = 1; w < S; ++w) m = fmaxf(m, red[w]);
+    const float m = strip_absmax(amax, g, max(SY0, 0), min(SY0 + g.SH, g.H) - 1, max(SX0, 0),
+                                 min(SX0 + g.SW, g.W) - 1);
     const int e = m > 0.f ? ilogbf(m) + 1 : 0;  // m < 2^e
     const int k = max(-60, min(60, 14 - e));
     scale = ldexpf(1.f, k);
@@ -327,15 +315,15 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
 template <class CT, int C, int KR, int NT>
 __global__ void __launch_bounds__(64 * fast_max_waves(CT::kSplit ? 1 : 0, C))
 xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
-                const float* __restrict__ centers, int* __restrict__ out_idx,
-                float* __restrict__ out_dist, const FastGeom g) {
+                const float* __restrict__ centers, const float* __restrict__ amax,
+                int* __restrict__ out_idx, float* __restrict__ out_dist, const FastGeom g) {
   extern __shared__ __align__(16) unsigned char lds[];
-  fast_block<CT, C, KR, NT>(img, nrm, centers, out_idx, out_dist, g,
+  fast_block<CT, C, KR, NT>(img, nrm, centers, amax, out_idx, out_dist, g,
                             xcd_remap(blockIdx.x, g.nwg_total), lds);
 }
 
-typedef void (*XcFastKernel)(const float*, const float*, const float*, int*, float*,
-                             const FastGeom);
+typedef void (*XcFastKernel)(const float*, const float*, const float*, const float*, int*,
+                             float*, const FastGeom);
 
 // policy for (precision, C, H2): 0 float32, 1 bfloat16 split, 2 float16 split
 template <int PREC, int C, int H2>

@@ -5,8 +5,8 @@
 
 namespace bmk {
 
-typedef void (*XcFastKernel)(const float*, const float*, const float*, int*, float*,
-                             const FastGeom);
+typedef void (*XcFastKernel)(const float*, const float*, const float*, const float*, int*,
+                             float*, const FastGeom);
 #define BMK_DECL(P)                                         \
   XcFastKernel fast_kernel_p##P##_c1(int h2, int kr, int nt); \
   XcFastKernel fast_kernel_p##P##_c2(int h2, int kr, int nt); \
@@ -35,12 +35,12 @@ hipError_t prepare_xcorr_fast(int prec, int c, int h2, int kr, int nt, int lds_b
 }
 
 hipError_t launch_xcorr_fast(int prec, int c, int h2, int kr, int nt, const float* img,
-                             const float* nrm, const float* centers, int* idx, float* dist,
-                             const XcGeom& g, hipStream_t stream) {
+                             const float* nrm, const float* centers, const float* amax,
+                             int* idx, float* dist, const XcGeom& g, hipStream_t stream) {
   XcFastKernel k = fast_kernel(prec, c, h2, kr, nt);
   if (!k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(g.nwg_total), dim3(64 * g.WS), g.lds_bytes, stream, img, nrm,
-                     centers, idx, dist, fast_geom(g));
+                     centers, amax, idx, dist, fast_geom(g));
   return hipGetLastError();
 }
 
