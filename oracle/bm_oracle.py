@@ -27,6 +27,12 @@ Readings taken where the paper is silent (each one is listed in the design notes
   the first K entries of the candidates sorted by the key (d, j);
 * fewer than K candidates: the row is padded with index -1 and distance +inf.
 
+* Normalized-cross-correlation BM (Sec. III-A, Eq. ``equ:cor``; Lemma 1; Theorem 1 item 3):
+  the K candidates with the largest vec(X_j)^T vec(X_i) / (||X_j||_F ||X_i||_F).  The
+  oracle reports them through the equivalent distance e = 2 - 2 NCC (the squared distance
+  between the unit-normalised patches), so the same ascending (e, j) order and padding
+  apply.  Reading: when either patch has zero norm its NCC is taken as 0 (e = 2).
+
 Parity status: every function below is pinned by the CPU test suite against hand-checked
 values, closed forms, library routines or brute force (see tests/test_oracle_pins.py).
 """
@@ -154,6 +160,50 @@ def bm(x: np.ndarray, P: int, s: int, Wn: int, K: int, refs=None):
         ry, rx = int(rl[i, 0]), int(rl[i, 1])
         d, j = window_distances(x64, P, Wn, ry, rx)
         idx[n], dist[n] = select_k(d, j, K)
+    return idx, dist
+
+
+# --------------------------------------------------------------------------------------
+# Normalized cross-correlation (Eq. equ:cor, Lemma 1)
+# --------------------------------------------------------------------------------------
+def window_ncc(x64: np.ndarray, P: int, Wn: int, ry: int, rx: int):
+    """NCC of one reference with every in-window candidate.
+
+    Returns (ncc, j) in row-major window order: the inner product of the vectorised patches
+    divided by the product of their Frobenius norms, float64; 0 when a norm is 0.
+    """
+    C, H, W = x64.shape
+    Hv, Wv = valid_extent(H, W, P)
+    y0, y1, x0, x1 = window_box(ry, rx, Hv, Wv, Wn)
+    cands = sliding_window_view(x64[:, y0:y1 + P, x0:x1 + P], (P, P), axis=(1, 2))
+    ref = x64[:, ry:ry + P, rx:rx + P]
+    dot = np.sum(cands * ref[:, None, None, :, :], axis=(0, 3, 4))
+    nq = np.sqrt(np.sum(cands * cands, axis=(0, 3, 4)))
+    npp = np.sqrt(np.sum(ref * ref))
+    den = nq * npp
+    ncc = np.where(den > 0, dot / np.where(den > 0, den, 1.0), 0.0)
+    j = (np.arange(y0, y1 + 1)[:, None] * W + np.arange(x0, x1 + 1)[None, :])
+    return ncc.ravel(), np.broadcast_to(j, ncc.shape).ravel().astype(np.int64)
+
+
+def bm_ncc(x: np.ndarray, P: int, s: int, Wn: int, K: int, refs=None):
+    """NCC block matching (Eq. equ:cor), float64 brute force.
+
+    Same arguments and layout as ``bm``; the returned distances are e = 2 - 2 NCC, rows
+    sorted ascending by (e, j), i.e. descending NCC with ties by the smaller index.
+    """
+    x64 = np.asarray(x, dtype=np.float64)
+    if x64.ndim == 2:
+        x64 = x64[None]
+    C, H, W = x64.shape
+    rl = ref_list(H, W, P, s)
+    sel = np.arange(len(rl)) if refs is None else np.asarray(refs, dtype=np.int64)
+    idx = np.empty((len(sel), K), dtype=np.int64)
+    dist = np.empty((len(sel), K), dtype=np.float64)
+    for n, i in enumerate(sel):
+        ry, rx = int(rl[i, 0]), int(rl[i, 1])
+        ncc, j = window_ncc(x64, P, Wn, ry, rx)
+        idx[n], dist[n] = select_k(2.0 - 2.0 * ncc, j, K)
     return idx, dist
 
 
