@@ -100,9 +100,9 @@ def cpu_baseline(img, sh, budget_s: float):
             "host_threads_available": len(os.sched_getaffinity(0))}
 
 
-def run_form(bm, torch, img_t, sh, prec, steps, warmup):
+def run_form(bm, torch, img_t, sh, prec, steps, warmup, flags=0):
     desc = bm.make_desc(sh.height, sh.width, sh.channels, sh.patch, sh.stride, sh.window,
-                        sh.k, prec)
+                        sh.k, prec, flags)
     plan = bm.bm_plan(desc)
     dev = img_t.device
     nrm = torch.empty(((sh.height - sh.patch + 1) * (sh.width - sh.patch + 1),),
@@ -190,6 +190,10 @@ def main():
     results = {}
     for prec in ["fp32", "bf16x3", "fp16x3"]:
         results[prec] = run_form(bm, torch, img_t, sh, prec, args.steps, args.warmup)
+    # the same workload ranked by normalized cross-correlation (BM_FLAG_NCC)
+    ncc = {}
+    for prec in ["fp32", "fp16x3"]:
+        ncc[prec] = run_form(bm, torch, img_t, sh, prec, args.steps, args.warmup, bm.BM_FLAG_NCC)
 
     prec = args.precision
     plan, wall, norm_ms, xc_ms, step_ms, _ = results[prec]
@@ -235,6 +239,10 @@ def main():
                     "p99_ms": quantile(sf, 0.99), "config": bm.bm_plan_config(pf)[0],
                     "roofline_frac": flops / xa / 1e12 / PEAK_TFLOPS[f]}
     out["forms"] = forms
+    out["ncc_forms"] = {
+        f: {"value": pf.n_ref * args.steps / wf, "cross_topk_ms": sum(xf) / len(xf),
+            "p50_ms": quantile(sf, 0.5), "p99_ms": quantile(sf, 0.99)}
+        for f, (pf, wf, nf, xf, sf, _) in ncc.items()}
     v32 = forms["fp32"]["value"]
     out["plain_fp32"] = {"value": v32, "speedup": value / v32}
     if args.cpu_budget > 0:

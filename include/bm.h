@@ -61,6 +61,14 @@ typedef int32_t bm_status;
 /* bm_desc.flags */
 #define BM_FLAG_CENTER 1u   /* subtract a per-channel mean before the cross term (the
                                distance is translation invariant; reduces cancellation) */
+#define BM_FLAG_NCC 2u      /* rank by normalized cross-correlation (Sec. III-A,
+                               Eq. (equ:cor); Lemma 1, Theorem 1 item 3): keep the K
+                               candidates with the largest <X_i, X_j> / (||X_i|| ||X_j||);
+                               dist reports 2 - 2 NCC in [0, 4] (the squared distance of the
+                               unit-normalised patches), ascending; NCC is 0 when either
+                               patch has zero norm.  Needs the specialised kernel (C <= 4,
+                               patch 3..8, K <= 32, 3*stride + window <= 48; BM_ENOTSUP
+                               otherwise); not combinable with BM_FLAG_CENTER (BM_EINVAL). */
 
 /* One BM problem, following the paper's statement of BM: image, patch size sqrt(n),
  * stride, search window, K (Sec. III-A; Sec. V-A fixes 6x6 patches, stride 1, 30x30). */

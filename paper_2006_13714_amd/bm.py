@@ -30,6 +30,7 @@ BM_PREC_FP16X3 = 2
 PRECISIONS = {"fp32": BM_PREC_FP32, "bf16x3": BM_PREC_BF16X3, "fp16x3": BM_PREC_FP16X3}
 
 BM_FLAG_CENTER = 1
+BM_FLAG_NCC = 2
 
 
 class bm_desc(C.Structure):

@@ -45,7 +45,10 @@ bm_status validate_desc(const bm_desc* d) {
     return fail(BM_EINVAL, "unknown precision %d", d->precision);
   if ((int64_t)d->height * d->width * d->channels >= (int64_t)1 << 31)
     return fail(BM_EINVAL, "image too large for 32-bit indexing");
-  if (d->flags & ~BM_FLAG_CENTER) return fail(BM_EINVAL, "unknown flag bits 0x%x", d->flags);
+  if (d->flags & ~(BM_FLAG_CENTER | BM_FLAG_NCC))
+    return fail(BM_EINVAL, "unknown flag bits 0x%x", d->flags);
+  if ((d->flags & BM_FLAG_CENTER) && (d->flags & BM_FLAG_NCC))
+    return fail(BM_EINVAL, "centring changes the normalized cross-correlation");
   const int pe = d->patch + (d->patch & 1);
   if (d->channels * (pe / 2) * (pe / 2) > kMaxSteps)
     return fail(BM_ENOTSUP, "channels * ceil(patch/2)^2 = %d exceeds %d",
@@ -97,6 +100,7 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) 
   g.SH = g.NH + prow - 1;
   g.SW = g.NW + pcol - 1;
   g.prec = d.precision;
+  g.metric = (d.flags & BM_FLAG_NCC) ? 1 : 0;
   g.RS = fast ? (d.precision == BM_PREC_FP32 ? kFastRS : kSplitRW) : g.SW;
   g.PLANE = g.SH * g.RS;
   g.CAP = cap;

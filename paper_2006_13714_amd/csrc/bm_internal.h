@@ -43,6 +43,7 @@ struct XcGeom {
   int step_off[kMaxSteps];
   uint32_t step_mask[kMaxSteps];
   int prec;             // BM_PREC_* of the launch
+  int metric;           // 0 Euclidean, 1 normalized cross-correlation
 };
 
 // The fields of XcGeom that the specialised kernel reads (kernel argument of the
@@ -53,6 +54,7 @@ struct FastGeom {
   int SH, SW, NH, CAP, p1_step;
   int lds_strip_off, lds_norm_off, lds_buf_off;
   int ntx, nty;  // tile grid of the norm pass (its per-tile max |x| map)
+  int metric;    // 0 Euclidean, 1 normalized cross-correlation
 };
 
 inline FastGeom fast_geom(const XcGeom& g) {
@@ -64,6 +66,7 @@ inline FastGeom fast_geom(const XcGeom& g) {
   f.lds_buf_off = g.lds_buf_off;
   f.ntx = (g.Wv + kNormTX - 1) / kNormTX;
   f.nty = (g.Hv + kNormTY - 1) / kNormTY;
+  f.metric = g.metric;
   return f;
 }
 

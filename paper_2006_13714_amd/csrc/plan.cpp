@@ -113,6 +113,8 @@ bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_
   if (!c.fast && d.precision != BM_PREC_FP32)
     return fail(BM_ENOTSUP, "split precision needs C <= 4, patch 5..8, K <= 32 and "
                             "3*stride + window <= 48");
+  if (!c.fast && (d.flags & BM_FLAG_NCC))
+    return fail(BM_ENOTSUP, "NCC needs C <= 4, patch 3..8, K <= 32 and 3*stride + window <= 48");
   p->geom = g;
   p->cfg = c;
   p->kr = kr_for(d.k);
@@ -157,6 +159,8 @@ static bm_status builtin_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
   if (d.precision != BM_PREC_FP32)
     return fail(BM_ENOTSUP, "split precision needs C <= 4, patch 5..8, K <= 32 and "
                             "3*stride + window <= 48 (and the LDS to stage it)");
+  if (d.flags & BM_FLAG_NCC)
+    return fail(BM_ENOTSUP, "NCC needs C <= 4, patch 3..8, K <= 32 and 3*stride + window <= 48");
   static const int shapes[][3] = {{2, 2, 64}, {1, 2, 64}, {2, 1, 64}, {1, 1, 64}, {1, 1, 32}};
   const int min_wg = 512;
   TileCfg chosen;

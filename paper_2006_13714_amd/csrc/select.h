@@ -47,6 +47,8 @@ struct RefSelect {
   float tl[4][TL];
   Entry* buf;    // this wave's buffers: reference (4*gp + v) at buf[(4*gp+v)*cap]
   int cap, K, p16, gp;
+  bool ncc = false;  // outputs 2 - 2 NCC = 2 + outk[v] * key instead of the distance
+  float outk[4] = {0.f, 0.f, 0.f, 0.f};
   unsigned long long grp_bits, below;
 
   __device__ __forceinline__ void init(Entry* wave_buf, int cap_, int K_, int lane,
@@ -147,7 +149,8 @@ struct RefSelect {
     }
   }
 
-  // Column v of the sorted lists -> outputs (distance clamped at 0, padding -> (-1, +inf)).
+  // Column v of the sorted lists -> outputs (distance clamped at 0, or 2 - 2 NCC clamped to
+  // [0, 4]; padding -> (-1, +inf)).
   __device__ __forceinline__ void write_col(int v, int* out_idx, float* out_dist, size_t ref,
                                             bool valid) const {
     if (!valid) return;
@@ -156,8 +159,10 @@ struct RefSelect {
       const int e = 16 * q + p16;
       if (e < K) {
         const bool none = Lj[v][q] == kNoIndex;
+        const float o = ncc ? fminf(fmaxf(fmaf(outk[v], Ld[v][q], 2.f), 0.f), 4.f)
+                            : fmaxf(Ld[v][q], 0.f);
         out_idx[ref * K + e] = none ? -1 : Lj[v][q];
-        out_dist[ref * K + e] = none ? INFINITY : fmaxf(Ld[v][q], 0.f);
+        out_dist[ref * K + e] = none ? INFINITY : o;
       }
     }
   }

@@ -24,6 +24,10 @@
 //    +inf for rows outside the row range (per row), so an excluded pair has d = +inf.
 //  * Software pipeline: each tile's matrix ops are interleaved with the epilogue
 //    arithmetic of the previous tile and the LDS reads of the next one.
+//  * Metric: Euclidean (Lemma 2) or normalized cross-correlation (Eq. equ:cor, Lemma 1).
+//    For NCC the norm strip holds -1/||X_j|| (times the split forms' post-scale), so the
+//    same epilogue multiply-add yields e'' = -<X_i, X_j> / ||X_j||, which orders a
+//    reference's candidates exactly like 2 - 2 NCC; outputs are 2 - 2 NCC = 2 + 2 e'' / ||X_i||.
 //  * Selection (select.h): a bounding sweep over every p1-th candidate row of each wave,
 //    a lane-wise merge of the S waves' bounding lists into one upper bound on each K-th
 //    distance, a selecting sweep over all rows, and an exact merge of the S waves' lists.
@@ -104,9 +108,12 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
     scale = ldexpf(1.f, k);
     mc = -2.f * ldexpf(1.f, -2 * k);
   }
+  const bool ncc = g.metric != 0;  // wave-uniform
+  const float post = -0.5f * mc;   // removes the split forms' pre-scale (power of two)
 
-  // ---- stage the strip (policy layout; zero outside the image) and the norm strip (+inf
-  //      outside the valid positions)
+  // ---- stage the strip (policy layout; zero outside the image) and the norm strip:
+  //      Euclidean ||X_j||^2 (+inf outside the valid positions), NCC -post/||X_j|| (0 for a
+  //      zero patch and outside the valid positions, which the column masks exclude)
   CT::stage(strip, img, g, SY0, SX0, wave, S, lane, center, scale);
   for (int y = wave; y < g.NH; y += S) {
     const int qy = SY0 + y;
@@ -115,7 +122,9 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
     float* dst = nstrip + y * NW;
     for (int x = lane; x < NW; x += 64) {
       const int qx = SX0 + x;
-      dst[x] = (yok & (qx >= 0) & (qx < g.Wv)) ? src[qx] : INFINITY;
+      const bool ok = yok & (qx >= 0) & (qx < g.Wv);
+      const float n = ok ? src[qx] : 0.f;
+      dst[x] = ncc ? (n > 0.f ? -post / sqrtf(n) : 0.f) : (ok ? n : INFINITY);
     }
   }
   __syncthreads();
@@ -145,11 +154,19 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
       valid[v] = (gp <= a_max) & (v <= b_max);
     }
     sel.init(buf_all + (size_t)wave * 16 * g.CAP, g.CAP, g.K, lane, norms, valid);
+    // NCC outputs 2 - 2 NCC = 2 + (2/||X_i||) e''; the strip holds -post/||X_i|| here
+    sel.ncc = ncc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sel.outk[v] = -2.f * norms[v] / post;
+    // column masks: the reference's window columns and the image's valid columns
 #pragma unroll
     for (int tx = 0; tx < NT; ++tx)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        nrx[tx][v] = ((unsigned)(kTileN * tx + p16 - s * v) <= (unsigned)r2) ? norms[v] : INFINITY;
+      for (int v = 0; v < 4; ++v) {
+        const bool inw = (unsigned)(kTileN * tx + p16 - s * v) <= (unsigned)r2;
+        const bool colok = (unsigned)(rxw - r + kTileN * tx + p16) < (unsigned)g.Wv;
+        nrx[tx][v] = (inw & colok) ? (ncc ? 0.f : norms[v]) : INFINITY;
+      }
   }
 
   const int qy_lo = max(0, ryw - r);
@@ -176,8 +193,12 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
       const int nqy = (TX + 1 < NT) ? qy : min(qy + stride, qy_hi);
       const int nrb = (nqy - SY0) * CRS + bl + ((TX + 1 < NT) ? kTileN * (TX + 1) : 0);
       const f4 acc = CT::chain_and_load(A, cur, nxt, strip, nrb);
-      const float nc = nstrip[p_nrow + p16 + kTileN * p_tx] + p_ybias;
-      auto res = arith(accp, nc, p_tx);
+      const float ns = nstrip[p_nrow + p16 + kTileN * p_tx];
+      // d = X * acc + (column part + Y): Euclidean X = mc, Y = ||X_j||^2 + row mask;
+      // NCC X = -post/||X_j||, Y = row mask
+      const float X = ncc ? ns : mc;
+      const float Y = ncc ? p_ybias : ns + p_ybias;
+      auto res = arith(accp, X, Y, p_tx);
       CT::schedule();
       __builtin_amdgcn_sched_barrier(0);
       post(res, p_jrow + kTileN * p_tx + p16);
@@ -214,14 +235,16 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
       if (i < nrows) row(std::integral_constant<int, 0>{});
     }
     // drain: epilogue of the last tile
-    const float nc = nstrip[p_nrow + p16 + kTileN * p_tx] + p_ybias;
-    post(arith(accp, nc, p_tx), p_jrow + kTileN * p_tx + p16);
+    const float ns = nstrip[p_nrow + p16 + kTileN * p_tx];
+    const float X = ncc ? ns : mc;
+    const float Y = ncc ? p_ybias : ns + p_ybias;
+    post(arith(accp, X, Y, p_tx), p_jrow + kTileN * p_tx + p16);
   };
 
   // ---- sweep 1: bounding lists over every p1-th row of this wave
   const int p1 = g.p1_step;
   sweep(qy_lo + wave * p1, S * p1,
-        [&](const f4& acc, float nc, int tx) __attribute__((always_inline)) {
+        [&](const f4& acc, float X, float Y, int tx) __attribute__((always_inline)) {
           float nt[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) nt[v] = nrx[0][v];
@@ -232,7 +255,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
               for (int v = 0; v < 4; ++v) nt[v] = nrx[q][v];
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            lane_insert<TL>(sel.tl[v], fmaf(mc, acc[v], nt[v] + nc));
+            lane_insert<TL>(sel.tl[v], fmaf(X, acc[v], nt[v] + Y));
           return 0;
         },
         [&](int, int) __attribute__((always_inline)) {});
@@ -259,7 +282,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
 
   // ---- sweep 2: select
   sweep(qy_lo + wave, S,
-        [&](const f4& acc, float nc, int tx) __attribute__((always_inline)) {
+        [&](const f4& acc, float X, float Y, int tx) __attribute__((always_inline)) {
           float nt[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) nt[v] = nrx[0][v];
@@ -271,7 +294,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
           Admit a;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            a.d[v] = fmaf(mc, acc[v], nt[v] + nc);
+            a.d[v] = fmaf(X, acc[v], nt[v] + Y);
             a.pass[v] = a.d[v] < sel.th[v];
           }
           return a;

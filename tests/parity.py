@@ -96,3 +96,59 @@ def check_exact(gpu_idx, gpu_dist, oidx, odist):
     """Bit-exact comparison for integer-valued inputs where float32 arithmetic is exact."""
     assert np.array_equal(np.asarray(gpu_idx), oidx)
     assert np.array_equal(np.asarray(gpu_dist).astype(np.float64), odist)
+
+
+# NCC tolerance on e = 2 - 2 NCC (absolute): float32 accumulation of n = P*P*C products
+# errs by at most n*u*||X_i||*||X_j|| (Cauchy-Schwarz), the reciprocal norms by a few u
+# each, so |de| <= 2 (n + 8) u ~ 3.1e-5 at n = 256; the split forms add their split
+# residual (float16: ~2^-22 relative, bfloat16 without lo*lo: ~2^-16 per product).
+NCC_TOL = {"fp32": 4e-5, "fp16x3": 4e-5, "bf16x3": 2e-4}
+
+
+def check_ncc(x, P, s, Wn, K, gpu_idx, gpu_dist, refs=None, tol=4e-5, report=None):
+    """NCC rows (e = 2 - 2 NCC) against the oracle: |e_gpu - e*| <= tol per returned pair,
+    and the set rule with tau = tol around the oracle's K-th value."""
+    x64 = np.asarray(x, dtype=np.float64)
+    if x64.ndim == 2:
+        x64 = x64[None]
+    C, H, W = x64.shape
+    rl = O.ref_list(H, W, P, s)
+    sel = np.arange(len(rl)) if refs is None else np.asarray(refs)
+    gpu_idx = np.asarray(gpu_idx)
+    gpu_dist = np.asarray(gpu_dist)
+    rep = report or ParityReport()
+    for row, i in enumerate(sel):
+        ry, rx = int(rl[i, 0]), int(rl[i, 1])
+        ncc, j = O.window_ncc(x64, P, Wn, ry, rx)
+        e = 2.0 - 2.0 * ncc
+        oidx, odist = O.select_k(e, j, K)
+        lookup = dict(zip(j.tolist(), e.tolist()))
+        gi, gd = gpu_idx[row], gpu_dist[row]
+        rep.n_refs += 1
+        kk = min(K, e.size)
+        if np.any(gi[kk:] != -1) or np.any(np.isfinite(gd[kk:])):
+            rep.tolerant_mismatch += 1
+            rep.messages.append(f"ref {i}: bad padding")
+            continue
+        members = gi[:kk].tolist()
+        if len(set(members)) != kk or any(m not in lookup for m in members):
+            rep.tolerant_mismatch += 1
+            rep.messages.append(f"ref {i}: non-candidate or duplicate indices")
+            continue
+        estar = np.array([lookup[m] for m in members])
+        err = np.abs(gd[:kk].astype(np.float64) - estar)
+        rep.rel.append(err)
+        if np.any(err > tol):
+            rep.tolerant_mismatch += 1
+            rep.messages.append(f"ref {i}: error {err.max():.3e}")
+        keys = list(zip(gd[:kk].tolist(), members))
+        if keys != sorted(keys):
+            rep.order_violations += 1
+        t = odist[kk - 1]
+        if set(members) != set(oidx[:kk].tolist()):
+            rep.strict_mismatch += 1
+            must = {int(a) for a, b in zip(j, e) if b < t - tol}
+            if np.any(estar > t + tol) or not must.issubset(set(members)):
+                rep.tolerant_mismatch += 1
+                rep.messages.append(f"ref {i}: set rule violated")
+    return rep

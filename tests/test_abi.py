@@ -110,3 +110,13 @@ def test_server_arguments_checked_on_host():
     assert lib.bm_poll(None, 1, None, None, None) == bm.BM_EINVAL
     assert lib.bm_cancel(None, 1) == bm.BM_EINVAL
     assert lib.bm_server_destroy(None) == bm.BM_EINVAL
+
+
+def test_ncc_with_centring_rejected_on_host():
+    bm = ensure_built()
+    with pytest.raises(bm.BMError) as ei:
+        bm.bm_plan(bm.make_desc(64, 64, 1, 8, 3, 39, 16, "fp32", bm.BM_FLAG_NCC | bm.BM_FLAG_CENTER))
+    assert ei.value.status == bm.BM_EINVAL
+    with pytest.raises(bm.BMError) as ei:
+        bm.bm_plan(bm.make_desc(64, 64, 1, 8, 3, 39, 16, "fp32", 4))
+    assert ei.value.status == bm.BM_EINVAL
