@@ -36,6 +36,11 @@ struct Admit {
   bool pass[4];
 };
 
+// Wave-wide vote into a scalar register pair (a uniform branch on it needs no vector op).
+__device__ __forceinline__ unsigned long long vote(bool p) {
+  return __builtin_amdgcn_ballot_w64(p);
+}
+
 template <int KR>
 struct RefSelect {
   static constexpr int TL = 2 * KR;
@@ -46,6 +51,7 @@ struct RefSelect {
   int Lj[4][KR];
   float tl[4][TL];
   Entry* buf;    // this wave's buffers: reference (4*gp + v) at buf[(4*gp+v)*cap]
+  Entry* bv[4];  // this lane's reference (4*gp + v) buffer
   int cap, K, p16, gp;
   bool ncc = false;  // outputs 2 - 2 NCC = 2 + outk[v] * key instead of the distance
   float outk[4] = {0.f, 0.f, 0.f, 0.f};
@@ -60,6 +66,8 @@ struct RefSelect {
     gp = lane >> 4;
     grp_bits = 0xFFFFull << (16 * gp);
     below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) bv[v] = buf + (4 * gp + v) * cap;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       nr[v] = norms[v];
@@ -113,12 +121,12 @@ struct RefSelect {
   __device__ __forceinline__ void flush() {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      for (int ch = 0; __any(ch * 16 < cnt[v]); ++ch) {
+      for (int ch = 0; vote(ch * 16 < cnt[v]); ++ch) {
         const int e = ch * 16 + p16;
         float cd = INFINITY;
         int cj = kNoIndex;
         if (e < cnt[v]) {
-          const Entry x = buf[(4 * gp + v) * cap + e];
+          const Entry x = bv[v][e];
           cd = x.d;
           cj = x.j;
         }
@@ -130,22 +138,28 @@ struct RefSelect {
     }
   }
 
+  // Append the passing (d, j) of each reference to its buffer in lane order: a lane's slot
+  // is the buffered count plus the passing lanes of its group below it (mbcnt).
   __device__ __forceinline__ void commit(const Admit& a, int jg) {
-    if (__any(a.pass[0] | a.pass[1] | a.pass[2] | a.pass[3])) {
+    // the votes are taken on the comparisons themselves (a.pass[v] == a.d[v] < th[v]), so
+    // they stay scalar masks
+    if (vote((a.d[0] < th[0]) | (a.d[1] < th[1]) | (a.d[2] < th[2]) | (a.d[3] < th[3]))) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const unsigned long long m = __ballot(a.pass[v]);
+        const bool pass = a.d[v] < th[v];
+        const unsigned long long m = vote(pass);
         if (m) {
           const unsigned long long gm = m & grp_bits;
-          if (a.pass[v]) {
-            const int pos = cnt[v] + __popcll(gm & below);
-            buf[(4 * gp + v) * cap + pos] = Entry{a.d[v], jg};
+          const unsigned lo = (unsigned)gm, hi = (unsigned)(gm >> 32);
+          if (pass) {
+            const int pos = __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, cnt[v]));
+            bv[v][pos] = Entry{a.d[v], jg};
           }
-          cnt[v] += __popcll(gm);
+          cnt[v] = __builtin_popcount(lo) + (__builtin_popcount(hi) + cnt[v]);
         }
       }
       const int lim = cap - 16;
-      if (__any((cnt[0] > lim) | (cnt[1] > lim) | (cnt[2] > lim) | (cnt[3] > lim))) flush();
+      if (vote((cnt[0] > lim) | (cnt[1] > lim) | (cnt[2] > lim) | (cnt[3] > lim))) flush();
     }
   }
 
