@@ -32,6 +32,10 @@ Readings taken where the paper is silent (each one is listed in the design notes
   oracle reports them through the equivalent distance e = 2 - 2 NCC (the squared distance
   between the unit-normalised patches), so the same ascending (e, j) order and padding
   apply.  Reading: when either patch has zero norm its NCC is taken as 0 (e = 2).
+* Non-local means (Sec. III-A, Eq. ``equ:nlm``; Prop. 1): for every reference X_i, the
+  weights s_i(j) = exp(-||X_j - X_i||^2 / b^2) / Theta_i over the candidates of its search
+  window, Theta_i their unnormalised sum, and the recovered patch sum_j s_i(j) X_j.  The
+  oracle returns Theta_i and the recovered patch (C x P x P) per reference.
 
 Parity status: every function below is pinned by the CPU test suite against hand-checked
 values, closed forms, library routines or brute force (see tests/test_oracle_pins.py).
@@ -205,6 +209,37 @@ def bm_ncc(x: np.ndarray, P: int, s: int, Wn: int, K: int, refs=None):
         ncc, j = window_ncc(x64, P, Wn, ry, rx)
         idx[n], dist[n] = select_k(2.0 - 2.0 * ncc, j, K)
     return idx, dist
+
+
+# --------------------------------------------------------------------------------------
+# Non-local means (Eq. equ:nlm, Prop. 1)
+# --------------------------------------------------------------------------------------
+def nlm(x: np.ndarray, P: int, s: int, Wn: int, b: float, refs=None):
+    """NLM weights over each reference's window, float64.
+
+    Returns (theta [n], patch [n, C, P, P]): Theta_i = sum_j exp(-d_ij / b^2) and the
+    weighted average sum_j s_i(j) X_j with s_i(j) = exp(-d_ij / b^2) / Theta_i, the d_ij
+    being the per-pair subtraction distances of ``window_distances``.
+    """
+    x64 = np.asarray(x, dtype=np.float64)
+    if x64.ndim == 2:
+        x64 = x64[None]
+    C, H, W = x64.shape
+    Hv, Wv = valid_extent(H, W, P)
+    rl = ref_list(H, W, P, s)
+    sel = np.arange(len(rl)) if refs is None else np.asarray(refs, dtype=np.int64)
+    theta = np.empty(len(sel), dtype=np.float64)
+    patch = np.empty((len(sel), C, P, P), dtype=np.float64)
+    for n, i in enumerate(sel):
+        ry, rx = int(rl[i, 0]), int(rl[i, 1])
+        d, _ = window_distances(x64, P, Wn, ry, rx)
+        w = np.exp(-d / (b * b))
+        y0, y1, x0, x1 = window_box(ry, rx, Hv, Wv, Wn)
+        cands = sliding_window_view(x64[:, y0:y1 + P, x0:x1 + P], (P, P), axis=(1, 2))
+        cands = cands.transpose(1, 2, 0, 3, 4).reshape(-1, C, P, P)  # row-major window order
+        theta[n] = w.sum()
+        patch[n] = np.tensordot(w, cands, axes=(0, 0)) / theta[n]
+    return theta, patch
 
 
 def bm_two_image(x: np.ndarray, y: np.ndarray, P: int, s: int, Wn: int, K: int):
