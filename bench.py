@@ -135,6 +135,34 @@ def run_form(bm, torch, img_t, sh, prec, steps, warmup, flags=0):
     return plan, wall, norm_ms, xc_ms, step_ms, (idx, dist)
 
 
+NLM_B = 2.2  # ~ sqrt(2 sigma^2 n) for the gray512 noise (sigma 50/255, n = 64)
+
+
+def run_nlm(bm, torch, img_t, sh, steps, warmup):
+    """bm_nlm on the same workload (norms + NLM kernel per step), timed with events."""
+    desc = bm.make_desc(sh.height, sh.width, sh.channels, sh.patch, sh.stride, sh.window,
+                        sh.k, "fp32")
+    plan = bm.bm_plan(desc)
+    dev = img_t.device
+    patch = torch.empty((plan.n_ref, sh.channels, sh.patch, sh.patch), dtype=torch.float32,
+                        device=dev)
+    theta = torch.empty((plan.n_ref,), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        bm.bm_nlm(plan, img_t, NLM_B, patch, theta, None, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        bm.bm_nlm(plan, img_t, NLM_B, patch, theta, None, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [a.elapsed_time(b) for a, b in ev], wall
+
+
 def quantile(v, q):
     s = sorted(v)
     k = min(len(s) - 1, max(0, int(round(q * (len(s) - 1)))))
@@ -194,6 +222,7 @@ def main():
     ncc = {}
     for prec in ["fp32", "fp16x3"]:
         ncc[prec] = run_form(bm, torch, img_t, sh, prec, args.steps, args.warmup, bm.BM_FLAG_NCC)
+    nlm_res = run_nlm(bm, torch, img_t, sh, args.steps, args.warmup)
 
     prec = args.precision
     plan, wall, norm_ms, xc_ms, step_ms, _ = results[prec]
@@ -239,6 +268,12 @@ def main():
                     "p99_ms": quantile(sf, 0.99), "config": bm.bm_plan_config(pf)[0],
                     "roofline_frac": flops / xa / 1e12 / PEAK_TFLOPS[f]}
     out["forms"] = forms
+    nlm_ms, nlm_wall = nlm_res
+    nlm_flops = 2 * flops  # cross term + weighted patch sum, per in-window pair
+    out["nlm"] = {"value": sh.n_ref * args.steps / nlm_wall, "unit": "ref-patches/s",
+                  "ms_per_step": nlm_wall / args.steps * 1e3, "b": NLM_B,
+                  "kernel_ms": sum(nlm_ms) / len(nlm_ms),
+                  "roofline_frac": nlm_flops / (sum(nlm_ms) / len(nlm_ms) / 1e3) / 1e12 / PEAK_TFLOPS["fp32"]}
     out["ncc_forms"] = {
         f: {"value": pf.n_ref * args.steps / wf, "cross_topk_ms": sum(xf) / len(xf),
             "p50_ms": quantile(sf, 0.5), "p99_ms": quantile(sf, 0.99)}

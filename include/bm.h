@@ -134,6 +134,19 @@ bm_status bm_batch_workspace(int32_t n, const bm_plan_t* plans, int64_t* bytes);
 
 bm_status bm_plan_destroy(bm_plan_t plan);
 
+/* ---- non-local means ---------------------------------------------------------------- */
+/* Non-local means over each reference's search window (Sec. III-A, Eq. (equ:nlm);
+ * Prop. 1): w_ij = exp(-||X_j - X_i||^2 / b^2) for every in-window candidate X_j, Theta_i =
+ * sum_j w_ij, and the recovered patch Y_i = sum_j w_ij X_j / Theta_i.  The distances come
+ * from Lemma 2 as in bm_match; the weighted sum is a second matrix-core contraction.
+ * d_patch receives n_ref * C * P * P floats (reference-major in grid order, then channel,
+ * row, column); d_theta (may be NULL) n_ref floats.  The plan must be float32 without
+ * flags and inside the specialised kernel's envelope (C <= 4, patch 3..8,
+ * 3*stride + window in 17..48; BM_ENOTSUP otherwise); its K is not used.  b: finite,
+ * > 0 (BM_EINVAL otherwise).  d_workspace as in bm_match.  Asynchronous on `stream`. */
+bm_status bm_nlm(bm_plan_t plan, const float* d_img, float b, float* d_patch, float* d_theta,
+                 void* d_workspace, void* stream);
+
 /* ---- autotuning ------------------------------------------------------------------- */
 /* Time every kernel configuration that can run desc's shape class (waves per reference
  * block or wave grid, bounding-sweep row step, candidate-buffer capacity) on the current

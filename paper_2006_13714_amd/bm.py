@@ -70,6 +70,8 @@ _SIGS = {
                                    C.c_void_p]),
     "bm_batch_workspace": (C.c_int32, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]),
     "bm_plan_destroy": (C.c_int32, [C.c_void_p]),
+    "bm_nlm": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.c_void_p]),
     "bm_server_create": (C.c_int32, [C.POINTER(bm_server_cfg), C.POINTER(C.c_void_p)]),
     "bm_submit": (C.c_int32, [C.c_void_p, C.POINTER(bm_desc), C.c_void_p, C.POINTER(C.c_uint64)]),
     "bm_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p,
@@ -206,6 +208,11 @@ def bm_match_batch(plans, imgs, idxs, dists, workspace=None, stream=None):
     _check(lib().bm_match_batch(n, P, I, X, D, _ptr(workspace), _stream(stream)), "bm_match_batch")
 
 
+def bm_nlm(plan: Plan, img, b: float, patch, theta=None, workspace=None, stream=None):
+    _check(lib().bm_nlm(plan.handle, _ptr(img), float(b), _ptr(patch), _ptr(theta),
+                        _ptr(workspace), _stream(stream)), "bm_nlm")
+
+
 def bm_plan_destroy(plan: Plan):
     plan.close()
 
@@ -267,6 +274,24 @@ def cached_plan(desc: bm_desc) -> Plan:
     if p is None:
         p = _plan_cache[key] = bm_plan(desc)
     return p
+
+
+def nlm(img, patch: int, stride: int, window: int, b: float, plan: Plan | None = None,
+        stream=None):
+    """Allocate outputs and run bm_nlm on a (C, H, W) float32 CUDA tensor: (theta, patch)."""
+    import torch
+    if img.dim() == 2:
+        img = img.unsqueeze(0)
+    if not img.is_cuda or img.dtype != torch.float32:
+        raise ValueError("img must be a float32 tensor on the GPU")
+    img = img.contiguous()
+    Cn, H, W = img.shape
+    if plan is None:
+        plan = cached_plan(make_desc(H, W, Cn, patch, stride, window, 16, "fp32", 0))
+    out = torch.empty((plan.n_ref, Cn, patch, patch), dtype=torch.float32, device=img.device)
+    theta = torch.empty((plan.n_ref,), dtype=torch.float32, device=img.device)
+    bm_nlm(plan, img, b, out, theta, None, stream)
+    return theta, out
 
 
 def match(img, patch: int, stride: int, window: int, k: int, precision="fp32", flags=0,

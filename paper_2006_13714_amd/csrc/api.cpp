@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -140,6 +141,11 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) 
 
 }  // namespace bmk
 
+namespace bmk {
+hipError_t launch_nlm(const float* img, const float* nrm, float* patch, float* theta,
+                      const XcGeom& g, float b, hipStream_t stream);
+}  // namespace bmk
+
 using namespace bmk;
 
 extern "C" {
@@ -221,6 +227,29 @@ bm_status bm_cross_topk(bm_plan_t plan, const float* d_img, const float* d_norm,
   if (!d_img || !d_norm || !d_idx || !d_dist) return fail(BM_EINVAL, "NULL device pointer");
   return run_cross_topk(*plan, d_img, d_norm, plan_aux(*plan, plan->ws), d_idx, d_dist,
                         (hipStream_t)stream);
+}
+
+bm_status bm_nlm(bm_plan_t plan, const float* d_img, float b, float* d_patch, float* d_theta,
+                 void* d_workspace, void* stream) {
+  if (!plan) return fail(BM_EINVAL, "plan is NULL");
+  if (!d_img || !d_patch) return fail(BM_EINVAL, "NULL device pointer");
+  if (!(b > 0.f) || !std::isfinite(b) || !(b * b > 0.f) || !std::isfinite(b * b))
+    return fail(BM_EINVAL, "b must be finite and > 0");
+  const bm_desc& d = plan->desc;
+  if (!plan->geom.fast || d.precision != BM_PREC_FP32 || d.flags != 0)
+    return fail(BM_ENOTSUP, "NLM needs a float32 plan without flags inside the specialised "
+                            "kernel's envelope");
+  void* ws = d_workspace ? d_workspace : plan->ws;
+  if (!ws) return fail(BM_EINVAL, "no workspace");
+  hipStream_t s = (hipStream_t)stream;
+  float* nrm = static_cast<float*>(ws);
+  bm_status st = run_norms(*plan, d_img, nrm, plan_aux(*plan, ws), s);
+  if (st != BM_OK) return st;
+  XcGeom g;
+  fill_geom(d, plan->cfg.wy < 4 ? plan->cfg.wy : 4, 1, plan->cfg.cap, true, g);
+  hipError_t e = launch_nlm(d_img, nrm, d_patch, d_theta, g, b, s);
+  if (e != hipSuccess) return hip_fail(e, "NLM launch");
+  return BM_OK;
 }
 
 bm_status bm_match(bm_plan_t plan, const float* d_img, int32_t* d_idx, float* d_dist,

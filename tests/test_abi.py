@@ -120,3 +120,9 @@ def test_ncc_with_centring_rejected_on_host():
     with pytest.raises(bm.BMError) as ei:
         bm.bm_plan(bm.make_desc(64, 64, 1, 8, 3, 39, 16, "fp32", 4))
     assert ei.value.status == bm.BM_EINVAL
+
+
+def test_nlm_arguments_checked_on_host():
+    bm = ensure_built()
+    lib = bm.lib()
+    assert lib.bm_nlm(None, None, 1.0, None, None, None, None) == bm.BM_EINVAL
