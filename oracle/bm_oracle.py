@@ -36,6 +36,10 @@ Readings taken where the paper is silent (each one is listed in the design notes
   weights s_i(j) = exp(-||X_j - X_i||^2 / b^2) / Theta_i over the candidates of its search
   window, Theta_i their unnormalised sum, and the recovered patch sum_j s_i(j) X_j.  The
   oracle returns Theta_i and the recovered patch (C x P x P) per reference.
+* Group gather and aggregation (Sec. IV, image reconstruction): the group of reference i is
+  Y_i = [X_{S_i(1)}, ..., X_{S_i(K)}] (padding entries give zero patches); aggregation
+  deposits every group patch back at its location S_i(k), summing over overlaps, and
+  divides each pixel by the number of deposited patches covering it (0 where none does).
 
 Parity status: every function below is pinned by the CPU test suite against hand-checked
 values, closed forms, library routines or brute force (see tests/test_oracle_pins.py).
@@ -240,6 +244,46 @@ def nlm(x: np.ndarray, P: int, s: int, Wn: int, b: float, refs=None):
         theta[n] = w.sum()
         patch[n] = np.tensordot(w, cands, axes=(0, 0)) / theta[n]
     return theta, patch
+
+
+# --------------------------------------------------------------------------------------
+# Group gather and aggregation (Sec. IV, image reconstruction)
+# --------------------------------------------------------------------------------------
+def gather_groups(x: np.ndarray, idx: np.ndarray, P: int) -> np.ndarray:
+    """Y_i for every row of ``idx`` [n, K]: groups [n, K, C, P, P], zero for index -1."""
+    x64 = np.asarray(x, dtype=np.float64)
+    C, H, W = x64.shape
+    n, K = idx.shape
+    out = np.zeros((n, K, C, P, P), dtype=np.float64)
+    for i in range(n):
+        for k in range(K):
+            j = int(idx[i, k])
+            if j < 0:
+                continue
+            qy, qx = j // W, j % W
+            out[i, k] = x64[:, qy:qy + P, qx:qx + P]
+    return out
+
+
+def aggregate_groups(groups: np.ndarray, idx: np.ndarray, C: int, H: int, W: int):
+    """Deposit every group patch at its location and normalise by the coverage count.
+
+    Returns (image [C, H, W] float64, count [H, W] int64); pixels no patch covers are 0.
+    """
+    n, K = idx.shape
+    P = groups.shape[-1]
+    acc = np.zeros((C, H, W), dtype=np.float64)
+    cnt = np.zeros((H, W), dtype=np.int64)
+    for i in range(n):
+        for k in range(K):
+            j = int(idx[i, k])
+            if j < 0:
+                continue
+            qy, qx = j // W, j % W
+            acc[:, qy:qy + P, qx:qx + P] += groups[i, k]
+            cnt[qy:qy + P, qx:qx + P] += 1
+    out = np.where(cnt > 0, acc / np.maximum(cnt, 1), 0.0)
+    return out, cnt
 
 
 def bm_two_image(x: np.ndarray, y: np.ndarray, P: int, s: int, Wn: int, K: int):
