@@ -163,6 +163,34 @@ def run_nlm(bm, torch, img_t, sh, steps, warmup):
     return [a.elapsed_time(b) for a, b in ev], wall
 
 
+def run_groups(bm, torch, img_t, sh, idx, steps):
+    """bm_gather and bm_aggregate of the K-groups of the reported form's result."""
+    plan = bm.cached_plan(bm.make_desc(sh.height, sh.width, sh.channels, sh.patch, sh.stride,
+                                       sh.window, sh.k, "fp32"))
+    dev = img_t.device
+    groups = torch.empty((plan.n_ref, sh.k, sh.channels, sh.patch, sh.patch),
+                         dtype=torch.float32, device=dev)
+    out = torch.empty_like(img_t)
+    ws = torch.empty((bm.bm_aggregate_workspace(plan),), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    bm.bm_gather(plan, img_t, idx, groups, stream)
+    bm.bm_aggregate(plan, groups, idx, out, ws, stream)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for a, b, c in ev:
+        a.record(stream)
+        bm.bm_gather(plan, img_t, idx, groups, stream)
+        b.record(stream)
+        bm.bm_aggregate(plan, groups, idx, out, ws, stream)
+        c.record(stream)
+    torch.cuda.synchronize()
+    g_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / steps
+    a_ms = sum(b.elapsed_time(c) for _, b, c in ev) / steps
+    gbytes = groups.numel() * 4
+    return {"gather_ms": g_ms, "aggregate_ms": a_ms, "group_bytes": gbytes,
+            "gather_write_GBps": gbytes / g_ms / 1e6, "aggregate_read_GBps": gbytes / a_ms / 1e6}
+
+
 def quantile(v, q):
     s = sorted(v)
     k = min(len(s) - 1, max(0, int(round(q * (len(s) - 1)))))
@@ -223,6 +251,7 @@ def main():
     for prec in ["fp32", "fp16x3"]:
         ncc[prec] = run_form(bm, torch, img_t, sh, prec, args.steps, args.warmup, bm.BM_FLAG_NCC)
     nlm_res = run_nlm(bm, torch, img_t, sh, args.steps, args.warmup)
+    grp = run_groups(bm, torch, img_t, sh, results[args.precision][5][0], min(args.steps, 50))
 
     prec = args.precision
     plan, wall, norm_ms, xc_ms, step_ms, _ = results[prec]
@@ -274,6 +303,7 @@ def main():
                   "ms_per_step": nlm_wall / args.steps * 1e3, "b": NLM_B,
                   "kernel_ms": sum(nlm_ms) / len(nlm_ms),
                   "roofline_frac": nlm_flops / (sum(nlm_ms) / len(nlm_ms) / 1e3) / 1e12 / PEAK_TFLOPS["fp32"]}
+    out["groups"] = grp
     out["ncc_forms"] = {
         f: {"value": pf.n_ref * args.steps / wf, "cross_topk_ms": sum(xf) / len(xf),
             "p50_ms": quantile(sf, 0.5), "p99_ms": quantile(sf, 0.99)}

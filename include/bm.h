@@ -134,6 +134,27 @@ bm_status bm_batch_workspace(int32_t n, const bm_plan_t* plans, int64_t* bytes);
 
 bm_status bm_plan_destroy(bm_plan_t plan);
 
+/* ---- patch groups -------------------------------------------------------------------- */
+/* Group gather (Sec. IV: Y_i = [X_{S_i(1)}, ..., X_{S_i(K)}]): for every reference i and
+ * k < K, d_groups[((i*K + k)*C + c)*P*P + l*P + m] = X_c[qy + l][qx + m] where
+ * d_idx[i*K + k] = qy*W + qx (the output layout of bm_match).  An index of -1, or one that
+ * names no valid patch position, gives a zero patch.  d_idx: n_ref*K int32; d_groups:
+ * n_ref*K*C*P*P floats.  Asynchronous on `stream`. */
+bm_status bm_gather(bm_plan_t plan, const float* d_img, const int32_t* d_idx, float* d_groups,
+                    void* stream);
+
+/* Aggregation (Sec. IV, image reconstruction): deposit every group patch d_groups[i][k]
+ * (layout as bm_gather) at the location d_idx[i*K + k] (skipped when it names no valid
+ * position), summing overlaps, and divide each pixel by the number of deposited patches
+ * covering it; pixels no patch covers are 0.  d_out: C*H*W floats.  Sums are formed in
+ * 64-bit fixed point with an exponent taken from the largest |value| (exact to one rounding
+ * per deposit, independent of ordering: bitwise deterministic); values must be finite.
+ * d_workspace: bm_aggregate_workspace bytes, or NULL (the library allocates and frees it,
+ * which synchronises `stream`).  Asynchronous on `stream`. */
+bm_status bm_aggregate_workspace(bm_plan_t plan, int64_t* bytes);
+bm_status bm_aggregate(bm_plan_t plan, const float* d_groups, const int32_t* d_idx, float* d_out,
+                       void* d_workspace, void* stream);
+
 /* ---- non-local means ---------------------------------------------------------------- */
 /* Non-local means over each reference's search window (Sec. III-A, Eq. (equ:nlm);
  * Prop. 1): w_ij = exp(-||X_j - X_i||^2 / b^2) for every in-window candidate X_j, Theta_i =

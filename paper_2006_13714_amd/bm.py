@@ -70,6 +70,10 @@ _SIGS = {
                                    C.c_void_p]),
     "bm_batch_workspace": (C.c_int32, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]),
     "bm_plan_destroy": (C.c_int32, [C.c_void_p]),
+    "bm_gather": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bm_aggregate_workspace": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "bm_aggregate": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]),
     "bm_nlm": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_float, C.c_void_p, C.c_void_p, C.c_void_p,
                            C.c_void_p]),
     "bm_server_create": (C.c_int32, [C.POINTER(bm_server_cfg), C.POINTER(C.c_void_p)]),
@@ -206,6 +210,22 @@ def bm_match_batch(plans, imgs, idxs, dists, workspace=None, stream=None):
     X = (C.c_void_p * n)(*[_ptr(t) for t in idxs])
     D = (C.c_void_p * n)(*[_ptr(t) for t in dists])
     _check(lib().bm_match_batch(n, P, I, X, D, _ptr(workspace), _stream(stream)), "bm_match_batch")
+
+
+def bm_gather(plan: Plan, img, idx, groups, stream=None):
+    _check(lib().bm_gather(plan.handle, _ptr(img), _ptr(idx), _ptr(groups), _stream(stream)),
+           "bm_gather")
+
+
+def bm_aggregate_workspace(plan: Plan) -> int:
+    out = C.c_int64()
+    _check(lib().bm_aggregate_workspace(plan.handle, C.byref(out)), "bm_aggregate_workspace")
+    return out.value
+
+
+def bm_aggregate(plan: Plan, groups, idx, out, workspace=None, stream=None):
+    _check(lib().bm_aggregate(plan.handle, _ptr(groups), _ptr(idx), _ptr(out), _ptr(workspace),
+                              _stream(stream)), "bm_aggregate")
 
 
 def bm_nlm(plan: Plan, img, b: float, patch, theta=None, workspace=None, stream=None):

@@ -144,6 +144,28 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) 
 namespace bmk {
 hipError_t launch_nlm(const float* img, const float* nrm, float* patch, float* theta,
                       const XcGeom& g, float b, hipStream_t stream);
+hipError_t launch_gather(const float* img, const int32_t* idx, float* groups, const GroupGeom& g,
+                         hipStream_t s);
+long long aggregate_workspace_bytes(const GroupGeom& g);
+hipError_t launch_aggregate(const float* groups, const int32_t* idx, float* out, void* ws,
+                            const GroupGeom& g, hipStream_t s);
+
+static GroupGeom group_geom(const bm_plan_s& p) {
+  GroupGeom g;
+  g.C = p.geom.C;
+  g.H = p.geom.H;
+  g.W = p.geom.W;
+  g.P = p.geom.P;
+  g.Hv = p.geom.Hv;
+  g.Wv = p.geom.Wv;
+  g.K = p.geom.K;
+  g.n_ref = (long long)p.geom.nry * p.geom.nrx;
+  const long long n = g.n_ref * g.K + 1;
+  int bits = 0;
+  while ((1ll << bits) < n) ++bits;
+  g.cnt_bits = bits;
+  return g;
+}
 }  // namespace bmk
 
 using namespace bmk;
@@ -227,6 +249,46 @@ bm_status bm_cross_topk(bm_plan_t plan, const float* d_img, const float* d_norm,
   if (!d_img || !d_norm || !d_idx || !d_dist) return fail(BM_EINVAL, "NULL device pointer");
   return run_cross_topk(*plan, d_img, d_norm, plan_aux(*plan, plan->ws), d_idx, d_dist,
                         (hipStream_t)stream);
+}
+
+bm_status bm_gather(bm_plan_t plan, const float* d_img, const int32_t* d_idx, float* d_groups,
+                    void* stream) {
+  if (!plan) return fail(BM_EINVAL, "plan is NULL");
+  if (!d_img || !d_idx || !d_groups) return fail(BM_EINVAL, "NULL device pointer");
+  hipError_t e = launch_gather(d_img, d_idx, d_groups, group_geom(*plan), (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "gather launch");
+  return BM_OK;
+}
+
+bm_status bm_aggregate_workspace(bm_plan_t plan, int64_t* bytes) {
+  if (!plan || !bytes) return fail(BM_EINVAL, "NULL argument");
+  *bytes = aggregate_workspace_bytes(group_geom(*plan));
+  return BM_OK;
+}
+
+bm_status bm_aggregate(bm_plan_t plan, const float* d_groups, const int32_t* d_idx, float* d_out,
+                       void* d_workspace, void* stream) {
+  if (!plan) return fail(BM_EINVAL, "plan is NULL");
+  if (!d_groups || !d_idx || !d_out) return fail(BM_EINVAL, "NULL device pointer");
+  const GroupGeom g = group_geom(*plan);
+  hipStream_t s = (hipStream_t)stream;
+  void* ws = d_workspace;
+  bool own = false;
+  if (!ws) {
+    if (hipMalloc(&ws, aggregate_workspace_bytes(g)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(BM_ENOMEM, "aggregation workspace");
+    }
+    own = true;
+  }
+  hipError_t e = launch_aggregate(d_groups, d_idx, d_out, ws, g, s);
+  bm_status st = e == hipSuccess ? BM_OK : hip_fail(e, "aggregation launch");
+  if (own) {
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(ws);
+    if (st == BM_OK && e2 != hipSuccess) st = hip_fail(e2, "hipStreamSynchronize");
+  }
+  return st;
 }
 
 bm_status bm_nlm(bm_plan_t plan, const float* d_img, float b, float* d_patch, float* d_theta,

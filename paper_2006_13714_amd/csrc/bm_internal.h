@@ -91,6 +91,13 @@ struct NormGeom {
   int H, W, C, P, Hv, Wv;
 };
 
+// Group gather / aggregation geometry (one plan's image, patch and K).
+struct GroupGeom {
+  int C, H, W, P, Hv, Wv, K;
+  long long n_ref;
+  int cnt_bits;  // ceil(log2(n_ref * K + 1)): headroom of the fixed-point sums
+};
+
 // Per-image outputs of the norm pass that the cross-term pass reads besides the norm map:
 // the centring constants (null unless centring) and the per-tile max |x - centre| map
 // (null unless the float16 split form, which derives its pre-scale from it).

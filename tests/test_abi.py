@@ -126,3 +126,13 @@ def test_nlm_arguments_checked_on_host():
     bm = ensure_built()
     lib = bm.lib()
     assert lib.bm_nlm(None, None, 1.0, None, None, None, None) == bm.BM_EINVAL
+
+
+def test_group_arguments_checked_on_host():
+    import ctypes as C
+    bm = ensure_built()
+    lib = bm.lib()
+    assert lib.bm_gather(None, None, None, None, None) == bm.BM_EINVAL
+    assert lib.bm_aggregate(None, None, None, None, None, None) == bm.BM_EINVAL
+    out = C.c_int64()
+    assert lib.bm_aggregate_workspace(None, C.byref(out)) == bm.BM_EINVAL
