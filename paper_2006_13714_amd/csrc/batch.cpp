@@ -103,7 +103,7 @@ void release_staging(Staging* s, hipStream_t st, bool recorded_copy) {
 struct Group {
   int prec, kr, nt, tier;
   std::vector<int> members;  // entry indices, in hand-out order
-  int ws = 4, lds = 0, items = 0, rec_off = 0;
+  int ws = 4, cap = 32, lds = 0, items = 0, rec_off = 0;
 };
 }  // namespace
 
@@ -202,16 +202,33 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
     std::stable_sort(g.members.begin(), g.members.end(), [&](int a, int b) {
       return block_cost(*e[a].plan) > block_cost(*e[b].plan);
     });
-    // waves per block: the largest of the members' tuned values that the group's kernel
-    // takes and at which every member's LDS layout fits
-    int want = 1;
-    for (int b : g.members) want = std::max(want, e[b].plan->cfg.wy);
-    g.ws = std::min(want, batch_max_waves(g.tier));
+    // block size and candidate-buffer size: the members' tuned (waves, capacity) pair that
+    // carries the most work (references x pixels x window positions), with the waves capped
+    // at what the group's kernel takes and lowered until every member's LDS layout fits.
+    // One pair serves the whole group: the launch takes the largest member's LDS, so a
+    // single member's larger block or buffer would lower the occupancy of all of them.
+    std::map<std::pair<int, int>, double> votes;
+    for (int b : g.members) {
+      const bm_desc& d = e[b].plan->desc;
+      const double nref = (double)((d.height - d.patch) / d.stride + 1) *
+                          ((d.width - d.patch) / d.stride + 1);
+      votes[{e[b].plan->cfg.wy, e[b].plan->cfg.cap}] +=
+          nref * d.channels * d.patch * d.patch * (double)d.window * d.window;
+    }
+    std::pair<int, int> best{4, 32};
+    double best_w = -1.0;
+    for (const auto& v : votes)
+      if (v.second > best_w) {
+        best = v.first;
+        best_w = v.second;
+      }
+    g.cap = best.second;
+    g.ws = std::max(1, std::min(best.first, batch_max_waves(g.tier)));
     for (; g.ws > 1; g.ws >>= 1) {
       bool fits = true;
       for (int b : g.members) {
         XcGeom t;
-        fill_geom(e[b].plan->desc, g.ws, 1, e[b].plan->cfg.cap, true, t);
+        fill_geom(e[b].plan->desc, g.ws, 1, g.cap, true, t);
         fits &= t.lds_bytes <= max_lds;
       }
       if (fits) break;
@@ -220,7 +237,7 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
     for (int b : g.members) {
       const bm_plan_s& p = *e[b].plan;
       XcGeom xg;
-      fill_geom(p.desc, g.ws, 1, p.cfg.cap, true, xg);
+      fill_geom(p.desc, g.ws, 1, g.cap, true, xg);
       xg.p1_step = p.cfg.p1;
       if (xg.lds_bytes > max_lds) {
         release_staging(stg, s, false);

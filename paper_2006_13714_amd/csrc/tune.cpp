@@ -6,7 +6,9 @@
 // reference-grid size buckets (the grid size changes the workgroup count and so the load
 // balance, not the per-workgroup code).  Winners live in a process-wide table that bm_plan
 // consults; with BM_TUNE_CACHE set they are also appended to that text file and loaded from
-// it on first use, one line per class: "<key> | <configuration string>".
+// it on first use, one line per class: "<key> | <configuration string>".  A table of the
+// same format measured on MI355X (tuned_gfx950.txt, beside the library) is loaded first.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -37,15 +39,12 @@ static std::string class_key(const bm_desc& d) {
   return buf;
 }
 
-static void load_cache_locked() {
-  if (g_loaded) return;
-  g_loaded = true;
-  const char* path = getenv("BM_TUNE_CACHE");
-  if (!path) return;
+static void load_table_file(const char* path) {
   FILE* f = fopen(path, "r");
   if (!f) return;
   char line[512];
   while (fgets(line, sizeof(line), f)) {
+    if (line[0] == '#') continue;
     char* bar = strchr(line, '|');
     if (!bar) continue;
     std::string key(line, bar - line);
@@ -57,6 +56,29 @@ static void load_cache_locked() {
     if (parse_cfg(cfg.c_str(), &c)) g_tuned[key] = cfg;
   }
   fclose(f);
+}
+
+// The table measured on MI355X that ships beside the library (tuned_gfx950.txt), used when
+// the current device is a gfx950; BM_TUNE_CACHE entries, read after it, take precedence.
+static void load_cache_locked() {
+  if (g_loaded) return;
+  g_loaded = true;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+      strncmp(prop.gcnArchName, "gfx950", 6) == 0) {
+    Dl_info info;
+    if (dladdr(reinterpret_cast<void*>(&load_table_file), &info) && info.dli_fname) {
+      std::string dir(info.dli_fname);
+      const size_t slash = dir.rfind('/');
+      dir = slash == std::string::npos ? std::string(".") : dir.substr(0, slash);
+      load_table_file((dir + "/tuned_gfx950.txt").c_str());
+    }
+  } else {
+    (void)hipGetLastError();
+  }
+  const char* path = getenv("BM_TUNE_CACHE");
+  if (path) load_table_file(path);
 }
 
 bool tuned_lookup(const bm_desc& d, TileCfg* out) {
