@@ -36,6 +36,15 @@ Readings taken where the paper is silent (each one is listed in the design notes
   weights s_i(j) = exp(-||X_j - X_i||^2 / b^2) / Theta_i over the candidates of its search
   window, Theta_i their unnormalised sum, and the recovered patch sum_j s_i(j) X_j.  The
   oracle returns Theta_i and the recovered patch (C x P x P) per reference.
+* 3D block matching (Sec. IV, 3D Self-Convolution; the multi-channel runtime setup of
+  Sec. V): the volume has q channels (frames, modalities); a patch is a d x P x P block
+  (d <= q consecutive channels) and the search window is Wn x Wn x c, so candidates also
+  come from other channel positions.  Readings: reference depths are every position
+  z = 0..q-d, spatial references on the stride-s grid as in 2D; the depth window holds the
+  c positions z - floor((c-1)/2) .. z - floor((c-1)/2) + c - 1 (c = 9: z-4..z+4; c = 2: z,
+  z+1), intersected with 0..q-d, never shifted; the candidate index is
+  j = (z' H + qy) W + qx and references are numbered depth-major, z * n_ref2d + (grid index);
+  ties and padding as in 2D.  c = 1 with d = q is plain multi-channel BM.
 * Group gather and aggregation (Sec. IV, image reconstruction): the group of reference i is
   Y_i = [X_{S_i(1)}, ..., X_{S_i(K)}] (padding entries give zero patches); aggregation
   deposits every group patch back at its location S_i(k), summing over overlaps, and
@@ -284,6 +293,57 @@ def aggregate_groups(groups: np.ndarray, idx: np.ndarray, C: int, H: int, W: int
             cnt[qy:qy + P, qx:qx + P] += 1
     out = np.where(cnt > 0, acc / np.maximum(cnt, 1), 0.0)
     return out, cnt
+
+
+# --------------------------------------------------------------------------------------
+# 3D block matching (Sec. IV, 3D Self-Convolution)
+# --------------------------------------------------------------------------------------
+def depth_window(z: int, Z: int, c: int):
+    """Inclusive depth range of the candidates of a reference at depth z (Z = q - d + 1)."""
+    lo = z - (c - 1) // 2
+    return max(0, lo), min(Z - 1, lo + c - 1)
+
+
+def window3d_distances(v64: np.ndarray, P: int, d: int, Wn: int, c: int, z: int, ry: int, rx: int):
+    """All in-window distances of the reference (z, ry, rx): per-pair subtraction over the
+    d x P x P blocks, float64.  Returns (dist, j), slab-major then row-major."""
+    q, H, W = v64.shape
+    Hv, Wv = valid_extent(H, W, P)
+    z0, z1 = depth_window(z, q - d + 1, c)
+    y0, y1, x0, x1 = window_box(ry, rx, Hv, Wv, Wn)
+    ref = v64[z:z + d, ry:ry + P, rx:rx + P]
+    qy = np.arange(y0, y1 + 1)[:, None]
+    qx = np.arange(x0, x1 + 1)[None, :]
+    ds, js = [], []
+    for zc in range(z0, z1 + 1):
+        cands = sliding_window_view(v64[zc:zc + d, y0:y1 + P, x0:x1 + P], (P, P), axis=(1, 2))
+        diff = cands - ref[:, None, None, :, :]
+        dd = np.sum(diff * diff, axis=(0, 3, 4))
+        ds.append(dd.ravel())
+        js.append(np.broadcast_to((zc * H + qy) * W + qx, dd.shape).ravel().astype(np.int64))
+    return np.concatenate(ds), np.concatenate(js)
+
+
+def bm3d(v: np.ndarray, P: int, d: int, s: int, Wn: int, c: int, K: int, refs=None):
+    """3D Euclidean block matching over a q x H x W volume, float64 brute force.
+
+    Returns (idx [n, K] int64, dist [n, K] float64) for the references numbered depth-major
+    (all (q - d + 1) * n_ref2d of them, or the numbers in ``refs``)."""
+    v64 = np.asarray(v, dtype=np.float64)
+    q, H, W = v64.shape
+    if not 1 <= d <= q:
+        raise ValueError("patch depth must be in [1, q]")
+    rl = ref_list(H, W, P, s)
+    n2 = len(rl)
+    n = (q - d + 1) * n2
+    sel = np.arange(n) if refs is None else np.asarray(refs, dtype=np.int64)
+    idx = np.empty((len(sel), K), dtype=np.int64)
+    dist = np.empty((len(sel), K), dtype=np.float64)
+    for m, i in enumerate(sel):
+        z, i2 = divmod(int(i), n2)
+        dd, jj = window3d_distances(v64, P, d, Wn, c, z, int(rl[i2, 0]), int(rl[i2, 1]))
+        idx[m], dist[m] = select_k(dd, jj, K)
+    return idx, dist
 
 
 def bm_two_image(x: np.ndarray, y: np.ndarray, P: int, s: int, Wn: int, K: int):
