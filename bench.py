@@ -191,6 +191,63 @@ def run_groups(bm, torch, img_t, sh, idx, steps):
             "gather_write_GBps": gbytes / g_ms / 1e6, "aggregate_read_GBps": gbytes / a_ms / 1e6}
 
 
+def run_volume(bm, torch, w, prec, steps, warmup):
+    """3D search (window_depth > 0) on a synthetic volume: bm_norms (one map per slab) +
+    bm_cross_topk per step, timed with events on the launch stream."""
+    sh = w.shape
+    desc = bm.make_desc(sh.height, sh.width, sh.planes, sh.patch, sh.stride, sh.window, sh.k,
+                        prec, 0, sh.patch_depth, sh.window_depth)
+    plan = bm.bm_plan(desc)
+    dev = torch.device("cuda:0")
+    vol = torch.from_numpy(w.image).to(dev)
+    Z = sh.planes - sh.patch_depth + 1
+    nrm = torch.empty((Z, sh.height - sh.patch + 1, sh.width - sh.patch + 1),
+                      dtype=torch.float32, device=dev)
+    idx = torch.empty((plan.n_ref, sh.k), dtype=torch.int32, device=dev)
+    dist = torch.empty((plan.n_ref, sh.k), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        bm.bm_norms(plan, vol, nrm, stream)
+        bm.bm_cross_topk(plan, vol, nrm, idx, dist, stream)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b, c in ev:
+        a.record(stream)
+        bm.bm_norms(plan, vol, nrm, stream)
+        b.record(stream)
+        bm.bm_cross_topk(plan, vol, nrm, idx, dist, stream)
+        c.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    xc = sum(b.elapsed_time(c) for _, b, c in ev) / steps
+    nm = sum(a.elapsed_time(b) for a, b, _ in ev) / steps
+    # pairs: every reference depth's clipped depth window times the clipped 2D window
+    slabs = sum(min(Z - 1, z - (sh.window_depth - 1) // 2 + sh.window_depth - 1)
+                - max(0, z - (sh.window_depth - 1) // 2) + 1 for z in range(Z))
+    pairs = slabs * pair_count(sh.height, sh.width, sh.patch, sh.stride, sh.window)
+    flops = 2.0 * sh.patch * sh.patch * sh.patch_depth * pairs
+    return {"value": plan.n_ref * steps / wall, "unit": "ref-patches/s",
+            "ms_per_step": wall / steps * 1e3, "norms_ms": nm, "cross_topk_ms": xc,
+            "pairs_per_s": pairs / (xc / 1e3), "roofline_frac": flops / (xc / 1e3) / 1e12 / PEAK_TFLOPS[prec],
+            "config": bm.bm_plan_config(plan)[0]}
+
+
+def volumes(bm, synth, torch, steps, warmup):
+    out = {}
+    for make in (synth.video20, synth.multimodal6):
+        w = make()
+        sh = w.shape
+        out[w.name] = {"shape": {"planes": sh.planes, "height": sh.height, "width": sh.width,
+                                 "patch": sh.patch, "patch_depth": sh.patch_depth,
+                                 "stride": sh.stride, "window": sh.window,
+                                 "window_depth": sh.window_depth, "k": sh.k,
+                                 "n_ref": sh.n_ref, "seed": w.seed}}
+        for prec in ("fp32", "fp16x3"):
+            out[w.name][prec] = run_volume(bm, torch, w, prec, steps, warmup)
+    return out
+
+
 def quantile(v, q):
     s = sorted(v)
     k = min(len(s) - 1, max(0, int(round(q * (len(s) - 1)))))
@@ -308,6 +365,7 @@ def main():
         f: {"value": pf.n_ref * args.steps / wf, "cross_topk_ms": sum(xf) / len(xf),
             "p50_ms": quantile(sf, 0.5), "p99_ms": quantile(sf, 0.99)}
         for f, (pf, wf, nf, xf, sf, _) in ncc.items()}
+    out["volumes"] = volumes(bm, synth, torch, max(3, args.steps // 20), 2)
     v32 = forms["fp32"]["value"]
     out["plain_fp32"] = {"value": v32, "speedup": value / v32}
     if args.cpu_budget > 0:

@@ -71,15 +71,29 @@ typedef int32_t bm_status;
                                otherwise); not combinable with BM_FLAG_CENTER (BM_EINVAL). */
 
 /* One BM problem, following the paper's statement of BM: image, patch size sqrt(n),
- * stride, search window, K (Sec. III-A; Sec. V-A fixes 6x6 patches, stride 1, 30x30). */
+ * stride, search window, K (Sec. III-A; Sec. V-A fixes 6x6 patches, stride 1, 30x30).
+ *
+ * 3D search (Sec. IV, 3D Self-Convolution; the multi-channel setups of Sec. V-A): with
+ * window_depth = c >= 1 the image is a volume of q = channels planes (frames, modalities),
+ * a patch is a d x P x P block of d = patch_depth consecutive planes, and the search window
+ * is Wn x Wn x c.  References: every depth z = 0..q-d times the 2D reference grid, numbered
+ * z * (2D reference count) + grid index (n_ref = (q-d+1) * 2D count).  Candidates of depth
+ * z: depths z - (c-1)/2 .. z - (c-1)/2 + c - 1 (integer division; c = 9: z-4..z+4, c = 2:
+ * z..z+1) intersected with 0..q-d, never shifted, times the clipped 2D window.  Returned
+ * indices are volume positions (z' * H + y) * W + x; order and padding as in 2D.  Needs the
+ * specialised kernel's envelope for a d-channel image (d <= 4, patch 3..8 (5..8 split),
+ * K <= 32, 3*stride + window <= 48), no flags (BM_ENOTSUP otherwise); q * H * W < 2^31.
+ * Both fields 0: the plain 2D problem. */
 typedef struct {
-  int32_t height, width, channels; /* image H, W, C; 1 <= C <= 8                        */
+  int32_t height, width, channels; /* image H, W, C; 1 <= C <= 8 (3D: q <= 65536)       */
   int32_t patch;                   /* patch side P, 1 <= P <= 16, P <= min(H, W)        */
   int32_t stride;                  /* reference-grid stride s >= 1                      */
   int32_t window;                  /* window side Wn, odd, >= 1                         */
   int32_t k;                       /* neighbours kept, 1 <= K <= 64                     */
   int32_t precision;               /* BM_PREC_*                                         */
   uint32_t flags;                  /* BM_FLAG_*                                         */
+  int32_t patch_depth;             /* 3D: planes per patch d, 1 <= d <= min(4, q); 2D: 0 */
+  int32_t window_depth;            /* 3D: depth window c >= 1; 2D: 0                    */
 } bm_desc;
 
 typedef struct bm_plan_s* bm_plan_t;
@@ -95,14 +109,15 @@ bm_status bm_plan(const bm_desc* desc, bm_plan_t* out);
 bm_status bm_plan_info(bm_plan_t plan, int64_t* n_ref, int64_t* workspace_bytes);
 
 /* Run BM on one image: patch norms (box filter), then the fused cross-term / distance /
- * top-K kernel.  d_img: C*H*W floats; d_idx, d_dist: n_ref*K each.  d_workspace: NULL to
+ * top-K kernel.  d_img: C*H*W floats (3D: the q*H*W volume); d_idx, d_dist: n_ref*K each.  d_workspace: NULL to
  * use the plan's own (then calls on one plan must not overlap in time), or
  * workspace_bytes of device memory owned by the caller.  Asynchronous on `stream`. */
 bm_status bm_match(bm_plan_t plan, const float* d_img, int32_t* d_idx, float* d_dist,
                    void* d_workspace, void* stream);
 
 /* Patch-norm map alone (the box filter, h_X (.) h_X of Sec. III-B): d_norm receives
- * (H-P+1)*(W-P+1) floats, row-major.  It also writes the plan's own workspace (centring
+ * (H-P+1)*(W-P+1) floats, row-major (3D plans: one such map per slab z = 0..q-d, stacked by
+ * z, each the norms of the d-plane blocks at that depth).  It also writes the plan's own workspace (centring
  * constants, and the per-tile maxima of |x| that BM_PREC_FP16X3 reads), which the next
  * bm_cross_topk on the same plan consumes: such pairs on one plan must not overlap in
  * time.  Asynchronous on `stream`. */
@@ -127,6 +142,7 @@ bm_status bm_cross_topk(bm_plan_t plan, const float* d_img, const float* d_norm,
  * synchronises `stream`); a workspace must not be reused before the call's work has
  * finished on `stream`.  n = 0 is a no-op.  Errors: BM_EINVAL (NULL plan or pointer, plan
  * from another device), BM_ENOTSUP, BM_ENOMEM, BM_EDEVICE. */
+/* 3D plans: BM_ENOTSUP. */
 bm_status bm_match_batch(int32_t n, const bm_plan_t* plans, const float* const* d_imgs,
                          int32_t* const* d_idx, float* const* d_dist, void* d_workspace,
                          void* stream);
@@ -140,6 +156,7 @@ bm_status bm_plan_destroy(bm_plan_t plan);
  * d_idx[i*K + k] = qy*W + qx (the output layout of bm_match).  An index of -1, or one that
  * names no valid patch position, gives a zero patch.  d_idx: n_ref*K int32; d_groups:
  * n_ref*K*C*P*P floats.  Asynchronous on `stream`. */
+/* 3D plans: BM_ENOTSUP. */
 bm_status bm_gather(bm_plan_t plan, const float* d_img, const int32_t* d_idx, float* d_groups,
                     void* stream);
 
@@ -151,6 +168,7 @@ bm_status bm_gather(bm_plan_t plan, const float* d_img, const int32_t* d_idx, fl
  * per deposit, independent of ordering: bitwise deterministic); values must be finite.
  * d_workspace: bm_aggregate_workspace bytes, or NULL (the library allocates and frees it,
  * which synchronises `stream`).  Asynchronous on `stream`. */
+/* 3D plans: BM_ENOTSUP. */
 bm_status bm_aggregate_workspace(bm_plan_t plan, int64_t* bytes);
 bm_status bm_aggregate(bm_plan_t plan, const float* d_groups, const int32_t* d_idx, float* d_out,
                        void* d_workspace, void* stream);
@@ -164,7 +182,8 @@ bm_status bm_aggregate(bm_plan_t plan, const float* d_groups, const int32_t* d_i
  * row, column); d_theta (may be NULL) n_ref floats.  The plan must be float32 without
  * flags and inside the specialised kernel's envelope (C <= 4, patch 3..8,
  * 3*stride + window in 17..48; BM_ENOTSUP otherwise); its K is not used.  b: finite,
- * > 0 (BM_EINVAL otherwise).  d_workspace as in bm_match.  Asynchronous on `stream`. */
+ * > 0 (BM_EINVAL otherwise).  d_workspace as in bm_match.  3D plans: BM_ENOTSUP.
+ * Asynchronous on `stream`. */
 bm_status bm_nlm(bm_plan_t plan, const float* d_img, float b, float* d_patch, float* d_theta,
                  void* d_workspace, void* stream);
 
@@ -176,7 +195,9 @@ bm_status bm_nlm(bm_plan_t plan, const float* d_img, float b, float* d_patch, fl
  * patch, stride, window, K/16, precision, coarse grid size) and used by later bm_plan calls
  * in this process; with the environment variable BM_TUNE_CACHE naming a file it is also
  * appended there and read back by later processes.  out_cfg (may be NULL) receives the
- * configuration string.  Synchronous.  Errors: BM_EINVAL, BM_ENOMEM, BM_EDEVICE. */
+ * configuration string.  A 3D descriptor is tuned as the 2D problem of one d-plane slab
+ * (the first d planes of d_img), which is the configuration 3D plans look up.
+ * Synchronous.  Errors: BM_EINVAL, BM_ENOMEM, BM_EDEVICE. */
 bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, char* out_cfg,
                       int32_t out_len);
 
@@ -214,7 +235,8 @@ bm_status bm_server_create(const bm_server_cfg* cfg, bm_server_t* out);
 
 /* Queue one request; the host image (C*H*W floats) is copied before the call returns.
  * Thread-safe.  BM_EBUSY when max_queue requests wait, the host arena is full, or the
- * request alone exceeds the device budget; BM_EINVAL / BM_ENOTSUP as bm_plan. */
+ * request alone exceeds the device budget; BM_EINVAL / BM_ENOTSUP as bm_plan (3D
+ * descriptors: BM_ENOTSUP). */
 bm_status bm_submit(bm_server_t srv, const bm_desc* desc, const float* host_img,
                     uint64_t* ticket);
 

@@ -36,7 +36,8 @@ BM_FLAG_NCC = 2
 class bm_desc(C.Structure):
     _fields_ = [("height", C.c_int32), ("width", C.c_int32), ("channels", C.c_int32),
                 ("patch", C.c_int32), ("stride", C.c_int32), ("window", C.c_int32),
-                ("k", C.c_int32), ("precision", C.c_int32), ("flags", C.c_uint32)]
+                ("k", C.c_int32), ("precision", C.c_int32), ("flags", C.c_uint32),
+                ("patch_depth", C.c_int32), ("window_depth", C.c_int32)]
 
 
 class bm_server_cfg(C.Structure):
@@ -144,9 +145,12 @@ def _stream(stream) -> int | None:
     return stream.cuda_stream
 
 
-def make_desc(height, width, channels, patch, stride, window, k, precision="fp32", flags=0):
+def make_desc(height, width, channels, patch, stride, window, k, precision="fp32", flags=0,
+              patch_depth=0, window_depth=0):
+    """A bm_desc; patch_depth / window_depth > 0 make it a 3D search over `channels` planes."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    return bm_desc(height, width, channels, patch, stride, window, k, prec, flags)
+    return bm_desc(height, width, channels, patch, stride, window, k, prec, flags, patch_depth,
+                   window_depth)
 
 
 class Plan:
@@ -294,6 +298,26 @@ def cached_plan(desc: bm_desc) -> Plan:
     if p is None:
         p = _plan_cache[key] = bm_plan(desc)
     return p
+
+
+def match3d(vol, patch: int, patch_depth: int, stride: int, window: int, window_depth: int,
+            k: int, precision="fp32", plan: Plan | None = None, stream=None):
+    """3D search over a (q, H, W) float32 CUDA tensor: d x P x P blocks, Wn x Wn x c windows.
+
+    Returns (idx, dist) of shape ((q - d + 1) * n_ref2d, k), references depth-major; indices
+    are volume positions (z * H + y) * W + x."""
+    import torch
+    if vol.dim() != 3 or not vol.is_cuda or vol.dtype != torch.float32:
+        raise ValueError("vol must be a (q, H, W) float32 tensor on the GPU")
+    vol = vol.contiguous()
+    q, H, W = vol.shape
+    if plan is None:
+        plan = cached_plan(make_desc(H, W, q, patch, stride, window, k, precision, 0,
+                                     patch_depth, window_depth))
+    idx = torch.empty((plan.n_ref, k), dtype=torch.int32, device=vol.device)
+    dist = torch.empty((plan.n_ref, k), dtype=torch.float32, device=vol.device)
+    bm_match(plan, vol, idx, dist, None, stream)
+    return idx, dist
 
 
 def nlm(img, patch: int, stride: int, window: int, b: float, plan: Plan | None = None,

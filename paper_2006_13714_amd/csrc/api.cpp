@@ -35,7 +35,18 @@ const char* last_error() { return g_err.c_str(); }
 bm_status validate_desc(const bm_desc* d) {
   if (!d) return fail(BM_EINVAL, "desc is NULL");
   if (d->height < 1 || d->width < 1) return fail(BM_EINVAL, "height/width must be >= 1");
-  if (d->channels < 1 || d->channels > 8) return fail(BM_EINVAL, "channels must be in [1, 8]");
+  const bool d3 = d->window_depth != 0 || d->patch_depth != 0;
+  if (d3) {
+    if (d->window_depth < 1) return fail(BM_EINVAL, "window_depth must be >= 1 (0 for 2D)");
+    if (d->channels < 1 || d->channels > 65536)
+      return fail(BM_EINVAL, "3D: channels (volume planes) must be in [1, 65536]");
+    if (d->patch_depth < 1 || d->patch_depth > d->channels)
+      return fail(BM_EINVAL, "patch_depth must be in [1, channels]");
+    if (d->patch_depth > 4) return fail(BM_ENOTSUP, "3D search takes patch_depth <= 4");
+    if (d->flags) return fail(BM_ENOTSUP, "3D search takes no flags");
+  } else if (d->channels < 1 || d->channels > 8) {
+    return fail(BM_EINVAL, "channels must be in [1, 8]");
+  }
   if (d->patch < 1 || d->patch > 16) return fail(BM_EINVAL, "patch must be in [1, 16]");
   if (d->patch > d->height || d->patch > d->width)
     return fail(BM_EINVAL, "patch %d larger than the image", d->patch);
@@ -51,9 +62,10 @@ bm_status validate_desc(const bm_desc* d) {
   if ((d->flags & BM_FLAG_CENTER) && (d->flags & BM_FLAG_NCC))
     return fail(BM_EINVAL, "centring changes the normalized cross-correlation");
   const int pe = d->patch + (d->patch & 1);
-  if (d->channels * (pe / 2) * (pe / 2) > kMaxSteps)
-    return fail(BM_ENOTSUP, "channels * ceil(patch/2)^2 = %d exceeds %d",
-                d->channels * (pe / 2) * (pe / 2), kMaxSteps);
+  const int pc = d3 ? d->patch_depth : d->channels;
+  if (pc * (pe / 2) * (pe / 2) > kMaxSteps)
+    return fail(BM_ENOTSUP, "channels * ceil(patch/2)^2 = %d exceeds %d", pc * (pe / 2) * (pe / 2),
+                kMaxSteps);
   return BM_OK;
 }
 
@@ -142,6 +154,7 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) 
 }  // namespace bmk
 
 namespace bmk {
+hipError_t prepare_xcorr_depth(int prec, int c, int h2, int kr, int nt, int lds_bytes);
 hipError_t launch_nlm(const float* img, const float* nrm, float* patch, float* theta,
                       const XcGeom& g, float b, hipStream_t stream);
 hipError_t launch_gather(const float* img, const int32_t* idx, float* groups, const GroupGeom& g,
@@ -202,9 +215,26 @@ bm_status bm_plan(const bm_desc* desc, bm_plan_t* out) {
   if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
   bm_plan_s* p = new (std::nothrow) bm_plan_s();
   if (!p) return fail(BM_ENOMEM, "host allocation failed");
-  p->desc = *desc;
+  p->desc = slab_desc(*desc);
   p->device = dev;
-  st = choose_config(*desc, max_lds, p);
+  if (desc->window_depth > 0) {
+    p->depth_q = desc->channels;
+    p->depth_c = desc->window_depth;
+    p->Z = desc->channels - desc->patch_depth + 1;
+  }
+  st = choose_config(p->desc, max_lds, p);
+  if (st == BM_OK && plan_is_3d(*p)) {
+    if (!p->geom.fast) {
+      st = fail(BM_ENOTSUP, "3D search needs patch 3..8 (5..8 split), K <= 32 and "
+                            "3*stride + window <= 48");
+    } else {
+      e = prepare_xcorr_depth(p->desc.precision, p->desc.channels, (p->desc.patch + 1) / 2,
+                              p->kr, p->geom.NT, p->geom.lds_bytes);
+      if (e != hipSuccess) st = hip_fail(e, "hipFuncSetAttribute");
+    }
+    if (st == BM_OK && (int64_t)p->geom.nwg_total * p->Z >= ((int64_t)1 << 31))
+      st = fail(BM_EINVAL, "3D problem too large for one launch");
+  }
   if (st != BM_OK) {
     delete p;
     return st;
@@ -225,7 +255,7 @@ bm_status bm_plan(const bm_desc* desc, bm_plan_t* out) {
 
 bm_status bm_plan_info(bm_plan_t plan, int64_t* n_ref, int64_t* workspace_bytes) {
   if (!plan) return fail(BM_EINVAL, "plan is NULL");
-  if (n_ref) *n_ref = (int64_t)plan->geom.nry * plan->geom.nrx;
+  if (n_ref) *n_ref = (int64_t)plan->Z * plan->geom.nry * plan->geom.nrx;
   if (workspace_bytes) *workspace_bytes = plan->ws_bytes;
   return BM_OK;
 }
@@ -254,6 +284,7 @@ bm_status bm_cross_topk(bm_plan_t plan, const float* d_img, const float* d_norm,
 bm_status bm_gather(bm_plan_t plan, const float* d_img, const int32_t* d_idx, float* d_groups,
                     void* stream) {
   if (!plan) return fail(BM_EINVAL, "plan is NULL");
+  if (plan_is_3d(*plan)) return fail(BM_ENOTSUP, "not available for a 3D plan");
   if (!d_img || !d_idx || !d_groups) return fail(BM_EINVAL, "NULL device pointer");
   hipError_t e = launch_gather(d_img, d_idx, d_groups, group_geom(*plan), (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "gather launch");
@@ -262,6 +293,7 @@ bm_status bm_gather(bm_plan_t plan, const float* d_img, const int32_t* d_idx, fl
 
 bm_status bm_aggregate_workspace(bm_plan_t plan, int64_t* bytes) {
   if (!plan || !bytes) return fail(BM_EINVAL, "NULL argument");
+  if (plan_is_3d(*plan)) return fail(BM_ENOTSUP, "not available for a 3D plan");
   *bytes = aggregate_workspace_bytes(group_geom(*plan));
   return BM_OK;
 }
@@ -269,6 +301,7 @@ bm_status bm_aggregate_workspace(bm_plan_t plan, int64_t* bytes) {
 bm_status bm_aggregate(bm_plan_t plan, const float* d_groups, const int32_t* d_idx, float* d_out,
                        void* d_workspace, void* stream) {
   if (!plan) return fail(BM_EINVAL, "plan is NULL");
+  if (plan_is_3d(*plan)) return fail(BM_ENOTSUP, "not available for a 3D plan");
   if (!d_groups || !d_idx || !d_out) return fail(BM_EINVAL, "NULL device pointer");
   const GroupGeom g = group_geom(*plan);
   hipStream_t s = (hipStream_t)stream;
@@ -294,6 +327,7 @@ bm_status bm_aggregate(bm_plan_t plan, const float* d_groups, const int32_t* d_i
 bm_status bm_nlm(bm_plan_t plan, const float* d_img, float b, float* d_patch, float* d_theta,
                  void* d_workspace, void* stream) {
   if (!plan) return fail(BM_EINVAL, "plan is NULL");
+  if (plan_is_3d(*plan)) return fail(BM_ENOTSUP, "not available for a 3D plan");
   if (!d_img || !d_patch) return fail(BM_EINVAL, "NULL device pointer");
   if (!(b > 0.f) || !std::isfinite(b) || !(b * b > 0.f) || !std::isfinite(b * b))
     return fail(BM_EINVAL, "b must be finite and > 0");

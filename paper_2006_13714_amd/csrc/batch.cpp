@@ -335,8 +335,10 @@ extern "C" {
 bm_status bm_batch_workspace(int32_t n, const bm_plan_t* plans, int64_t* bytes) {
   if (!bytes) return fail(BM_EINVAL, "bytes is NULL");
   if (n < 0 || (n > 0 && !plans)) return fail(BM_EINVAL, "invalid batch");
-  for (int b = 0; b < n; ++b)
+  for (int b = 0; b < n; ++b) {
     if (!plans[b]) return fail(BM_EINVAL, "plan %d is NULL", b);
+    if (plan_is_3d(*plans[b])) return fail(BM_ENOTSUP, "plan %d is a 3D plan", b);
+  }
   *bytes = n == 0 ? 0 : batch_ws_layout(n, plans, nullptr);
   return BM_OK;
 }
@@ -347,8 +349,10 @@ bm_status bm_match_batch(int32_t n, const bm_plan_t* plans, const float* const* 
   if (n < 0) return fail(BM_EINVAL, "n < 0");
   if (n == 0) return BM_OK;
   if (!plans || !d_imgs || !d_idx || !d_dist) return fail(BM_EINVAL, "NULL array");
-  for (int b = 0; b < n; ++b)
+  for (int b = 0; b < n; ++b) {
     if (!plans[b]) return fail(BM_EINVAL, "plan %d is NULL", b);
+    if (plan_is_3d(*plans[b])) return fail(BM_ENOTSUP, "plan %d is a 3D plan", b);
+  }
   std::vector<int64_t> offs;
   const int64_t bytes = batch_ws_layout(n, plans, &offs);
   hipStream_t s = (hipStream_t)stream;

@@ -48,6 +48,12 @@ struct XcGeom {
 
 // The fields of XcGeom that the specialised kernel reads (kernel argument of the
 // single-image launch; per-image record of the batch launch).
+// 3D search: Z = q - d + 1 slabs (reference depths), the depth window holds depths
+// z - before .. z - before + c - 1 (clipped to 0..Z-1), `tiles` max-map entries per slab.
+struct DepthGeom {
+  int Z, before, c, tiles;
+};
+
 struct FastGeom {
   int H, W, Hv, Wv, P, s, r, K;
   int nry, nrx, nwg_x, nwg_total;

@@ -20,6 +20,10 @@ hipError_t launch_xcorr_f32(int ks_bucket, int kr, const float* img, const float
 int f32_step_bucket(int ks);
 hipError_t prepare_xcorr_f32(int ks_bucket, int kr, int lds_bytes);
 hipError_t prepare_xcorr_fast(int prec, int c, int h2, int kr, int nt, int lds_bytes);
+hipError_t prepare_xcorr_depth(int prec, int c, int h2, int kr, int nt, int lds_bytes);
+hipError_t launch_xcorr_depth(int prec, int c, int h2, int kr, int nt, const float* vol,
+                              const float* nrm, const float* amax, int* idx, float* dist,
+                              const XcGeom& g, const DepthGeom& dg, hipStream_t stream);
 hipError_t launch_xcorr_fast(int prec, int c, int h2, int kr, int nt, const float* img,
                              const float* nrm, const float* centers, const float* amax,
                              int* idx, float* dist, const XcGeom& g, hipStream_t stream);
@@ -75,7 +79,20 @@ int64_t desc_workspace_bytes(const bm_desc& d) {
   return align256(hv * wv * 4) + 256 + align256(norm_tile_count(d) * 4);
 }
 
-int64_t plan_workspace_bytes(const bm_plan_s& p) { return desc_workspace_bytes(p.desc); }
+bm_desc slab_desc(const bm_desc& d) {
+  bm_desc t = d;
+  if (d.window_depth > 0) t.channels = d.patch_depth;
+  t.patch_depth = 0;
+  t.window_depth = 0;
+  return t;
+}
+
+// 3D plans stack Z norm maps, and Z per-tile max maps in the auxiliary region
+int64_t plan_workspace_bytes(const bm_plan_s& p) {
+  if (!plan_is_3d(p)) return desc_workspace_bytes(p.desc);
+  const int64_t hv = p.geom.Hv, wv = p.geom.Wv;
+  return align256(p.Z * hv * wv * 4) + 256 + align256(p.Z * norm_tile_count(p.desc) * 4);
+}
 
 bool plan_needs_centers(const bm_plan_s& p) { return (p.desc.flags & BM_FLAG_CENTER) != 0; }
 
@@ -90,7 +107,7 @@ NormAux aux_at(const bm_plan_s& p, void* slot) {
 
 NormAux plan_aux(const bm_plan_s& p, void* ws) {
   if (!ws) return NormAux{nullptr, nullptr};
-  return aux_at(p, static_cast<char*>(ws) + align256((int64_t)p.geom.Hv * p.geom.Wv * 4));
+  return aux_at(p, static_cast<char*>(ws) + align256((int64_t)p.Z * p.geom.Hv * p.geom.Wv * 4));
 }
 
 bool fast_eligible(const bm_desc& d) {
@@ -216,8 +233,14 @@ bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, const
     if (e != hipSuccess) return hip_fail(e, "centring launch");
   }
   NormGeom ng{g.H, g.W, g.C, g.P, g.Hv, g.Wv};
-  e = launch_norm(d_img, d_norm, ng, aux.centers, aux.amax, s);
-  if (e != hipSuccess) return hip_fail(e, "norm launch");
+  // 3D: one norm map (and max map) per d-plane slab, stacked by depth
+  const size_t plane = (size_t)g.H * g.W, nmap = (size_t)g.Hv * g.Wv;
+  const size_t tiles = (size_t)norm_tile_count(p.desc);
+  for (int z = 0; z < p.Z; ++z) {
+    e = launch_norm(d_img + z * plane, d_norm + z * nmap, ng, aux.centers,
+                    aux.amax ? aux.amax + z * tiles : nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "norm launch");
+  }
   return BM_OK;
 }
 
@@ -225,6 +248,14 @@ bm_status run_cross_topk(const bm_plan_s& p, const float* d_img, const float* d_
                          const NormAux& aux, int32_t* d_idx, float* d_dist, hipStream_t s) {
   const bm_desc& d = p.desc;
   if (d.precision == BM_PREC_FP16X3 && !aux.amax) return fail(BM_EINVAL, "no max map slot");
+  if (plan_is_3d(p)) {
+    const DepthGeom dg{p.Z, (p.depth_c - 1) / 2, p.depth_c, (int)norm_tile_count(d)};
+    hipError_t e = launch_xcorr_depth(d.precision, d.channels, (d.patch + 1) / 2, p.kr,
+                                      p.geom.NT, d_img, d_norm, aux.amax, d_idx, d_dist, p.geom,
+                                      dg, s);
+    if (e != hipSuccess) return hip_fail(e, "3D cross-term launch");
+    return BM_OK;
+  }
   hipError_t e = p.geom.fast
                      ? launch_xcorr_fast(d.precision, d.channels, (d.patch + 1) / 2, p.kr,
                                          p.geom.NT, d_img, d_norm, aux.centers, aux.amax, d_idx,

@@ -32,7 +32,12 @@ struct bm_plan_s {
   void* ws = nullptr;   // plan-owned workspace (norm map)
   int64_t ws_bytes = 0;
   int cfg_source = 0;   // 0 built-in rule, 1 autotuner table, 2 BM_CFG override
+  // 3D search: `desc` is then the 2D problem of one d-plane slab (channels = d) and these
+  // hold the volume's planes q, the depth window c and the slab count Z = q - d + 1
+  int depth_q = 0, depth_c = 0, Z = 1;
 };
+
+inline bool plan_is_3d(const bm_plan_s& p) { return p.depth_c > 0; }
 
 namespace bmk {
 
@@ -43,6 +48,8 @@ bm_status validate_desc(const bm_desc* d);
 void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g);
 
 bool fast_eligible(const bm_desc& d);
+// The 2D problem of one slab of a 3D descriptor (channels = patch_depth); 2D: d itself.
+bm_desc slab_desc(const bm_desc& d);
 bm_status choose_config(const bm_desc& d, int max_lds, bm_plan_s* p);
 bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_s* p);
 int64_t plan_workspace_bytes(const bm_plan_s& p);

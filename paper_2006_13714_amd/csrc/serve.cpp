@@ -220,6 +220,7 @@ bm_status bm_submit(bm_server_t srv, const bm_desc* desc, const float* host_img,
   if (!srv || !desc || !host_img || !ticket) return fail(BM_EINVAL, "NULL argument");
   bm_status st = validate_desc(desc);
   if (st != BM_OK) return st;
+  if (desc->window_depth > 0) return fail(BM_ENOTSUP, "the server takes 2D requests");
   if (desc->precision != BM_PREC_FP32 && !fast_eligible(*desc))
     return fail(BM_ENOTSUP, "split precision needs C <= 4, patch 5..8, K <= 32 and "
                             "3*stride + window <= 48");

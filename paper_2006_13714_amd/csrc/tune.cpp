@@ -156,7 +156,9 @@ bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, cha
   bm_status st = validate_desc(desc);
   if (st != BM_OK) return st;
   if (reps < 1 || reps > 1000) return fail(BM_EINVAL, "reps must be in [1, 1000]");
-  const bm_desc& d = *desc;
+  // a 3D descriptor tunes the 2D problem of one slab (its first d planes), which is the
+  // configuration its plans look up
+  const bm_desc d = slab_desc(*desc);
   int dev = 0, max_lds = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");

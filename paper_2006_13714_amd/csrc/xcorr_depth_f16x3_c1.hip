@@ -1,0 +1,9 @@
+// 3D search kernels (cross-term / top-K over a depth window of slabs): precision form
+// f16x3, 1-plane patches.
+#include "xcorr_fast.h"
+
+namespace bmk {
+
+XcDepthKernel depth_kernel_p2_c1(int h2, int kr, int nt) { return depth_h2<2, 1>(h2, kr, nt); }
+
+}  // namespace bmk

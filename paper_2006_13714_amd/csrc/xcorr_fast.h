@@ -58,18 +58,33 @@ __device__ __forceinline__ float strip_absmax(const float* __restrict__ amax, co
   return m;
 }
 
+// Candidate slabs of a 3D search (Sec. IV, 3D Self-Convolution): the reference's d-channel
+// slab is the one passed to fast_block as `img` / `nrm`; its candidates come from the
+// d-channel slabs z0..z1 of the volume (channel planes of H x W), each with its own norm map
+// (Hv x Wv) and, in the float16 form, its own per-tile max map.
+struct DepthWin {
+  const float* vol;
+  const float* nrm;
+  const float* amax;
+  int z0, z1;
+  int tiles;  // entries of one slab's max map
+};
+
 // One 4 x 4 reference block `blk` (row-major over the block grid) of one image, computed by
 // the whole workgroup (blockDim.x / 64 waves).  `centers` holds the per-channel centring
 // constants or is null; `amax` is the norm pass's per-tile max map (float16 form only).
-// Every thread of the workgroup must call it (it synchronises).
-template <class CT, int C, int KR, int NT>
+// Every thread of the workgroup must call it (it synchronises).  With D3 the candidates
+// are those of the slabs in `dw` (visited in increasing depth, restaged per slab, one
+// selection state across all of them) and indices are volume positions (z' H + qy) W + qx.
+template <class CT, int C, int KR, int NT, bool D3 = false>
 __device__ __forceinline__ void fast_block(const float* __restrict__ img,
                                            const float* __restrict__ nrm,
                                            const float* __restrict__ centers,
                                            const float* __restrict__ amax,
                                            int* __restrict__ out_idx,
                                            float* __restrict__ out_dist, const FastGeom& g,
-                                           int blk, unsigned char* lds) {
+                                           int blk, unsigned char* lds,
+                                           const DepthWin* dw = nullptr) {
   constexpr int CRS = CT::CRS;
   constexpr int NB = CT::NB;
   using BReg = std::conditional_t<std::is_same_v<typename CT::AReg, float>, float, uint32_t>;
@@ -101,8 +116,16 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
 #pragma unroll
   for (int c = 0; c < 8; ++c) center[c] = (centers && c < C) ? centers[c] : 0.f;
   if constexpr (CT::kScaled) {
-    const float m = strip_absmax(amax, g, max(SY0, 0), min(SY0 + g.SH, g.H) - 1, max(SX0, 0),
-                                 min(SX0 + g.SW, g.W) - 1);
+    const int y0 = max(SY0, 0), y1 = min(SY0 + g.SH, g.H) - 1;
+    const int x0 = max(SX0, 0), x1 = min(SX0 + g.SW, g.W) - 1;
+    float m;
+    if constexpr (D3) {  // one scale for every slab the block stages (the reference's included)
+      m = 0.f;
+      for (int zc = dw->z0; zc <= dw->z1; ++zc)
+        m = fmaxf(m, strip_absmax(dw->amax + (size_t)zc * dw->tiles, g, y0, y1, x0, x1));
+    } else {
+      m = strip_absmax(amax, g, y0, y1, x0, x1);
+    }
     const int e = m > 0.f ? ilogbf(m) + 1 : 0;  // m < 2^e
     const int k = max(-60, min(60, 14 - e));
     scale = ldexpf(1.f, k);
@@ -114,19 +137,23 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
   // ---- stage the strip (policy layout; zero outside the image) and the norm strip:
   //      Euclidean ||X_j||^2 (+inf outside the valid positions), NCC -post/||X_j|| (0 for a
   //      zero patch and outside the valid positions, which the column masks exclude)
-  CT::stage(strip, img, g, SY0, SX0, wave, S, lane, center, scale);
-  for (int y = wave; y < g.NH; y += S) {
-    const int qy = SY0 + y;
-    const bool yok = (qy >= 0) & (qy < g.Hv);
-    const float* src = nrm + (size_t)(yok ? qy : 0) * g.Wv;
-    float* dst = nstrip + y * NW;
-    for (int x = lane; x < NW; x += 64) {
-      const int qx = SX0 + x;
-      const bool ok = yok & (qx >= 0) & (qx < g.Wv);
-      const float n = ok ? src[qx] : 0.f;
-      dst[x] = ncc ? (n > 0.f ? -post / sqrtf(n) : 0.f) : (ok ? n : INFINITY);
+  auto stage_slab = [&](const float* __restrict__ im, const float* __restrict__ nm)
+                        __attribute__((always_inline)) {
+    CT::stage(strip, im, g, SY0, SX0, wave, S, lane, center, scale);
+    for (int y = wave; y < g.NH; y += S) {
+      const int qy = SY0 + y;
+      const bool yok = (qy >= 0) & (qy < g.Hv);
+      const float* src = nm + (size_t)(yok ? qy : 0) * g.Wv;
+      float* dst = nstrip + y * NW;
+      for (int x = lane; x < NW; x += 64) {
+        const int qx = SX0 + x;
+        const bool ok = yok & (qx >= 0) & (qx < g.Wv);
+        const float n = ok ? src[qx] : 0.f;
+        dst[x] = ncc ? (n > 0.f ? -post / sqrtf(n) : 0.f) : (ok ? n : INFINITY);
+      }
     }
-  }
+  };
+  stage_slab(img, nrm);
   __syncthreads();
 
   const int a_max = min(3, g.nry - 1 - RYw);
@@ -174,6 +201,23 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
   const int xs = rxw - r;  // first candidate column of the block
   const int bl = lane_off + p16;  // operand B lane offset within a strip row
 
+  // Candidate index of (slab, row 0, column 0): 0 in 2D; set per slab by over_slabs.
+  int jofs = 0;
+  // Runs `body` once (2D), or once per candidate slab after restaging the strips (3D).
+  auto over_slabs = [&](auto&& body) __attribute__((always_inline)) {
+    if constexpr (!D3) {
+      body();
+    } else {
+      for (int zc = dw->z0; zc <= dw->z1; ++zc) {
+        __syncthreads();  // every wave is done with the strips
+        stage_slab(dw->vol + (size_t)zc * g.H * g.W, dw->nrm + (size_t)zc * g.Hv * g.Wv);
+        __syncthreads();
+        jofs = zc * g.H * g.W;
+        body();
+      }
+    }
+  };
+
   // One sweep over rows first, first + stride, ... (<= qy_hi) of this wave.  `arith` runs
   // inside the pipelined region on the previous tile; `post` may branch.
   auto sweep = [&](int first, int stride, auto&& arith, auto&& post) __attribute__((always_inline)) {
@@ -207,7 +251,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
       if constexpr (TX == 0) {
         p_ybias = ((unsigned)(qy - ryw - s * gp + r) <= (unsigned)r2) ? 0.f : INFINITY;
         p_nrow = (qy - SY0) * NW;
-        p_jrow = qy * W + xs;
+        p_jrow = jofs + qy * W + xs;
       }
     };
     // tile TX of a row with buffer parity PAR uses buffer (PAR + TX) % 2 for its operands
@@ -243,6 +287,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
 
   // ---- sweep 1: bounding lists over every p1-th row of this wave
   const int p1 = g.p1_step;
+  over_slabs([&]() __attribute__((always_inline)) {
   sweep(qy_lo + wave * p1, S * p1,
         [&](const f4& acc, float X, float Y, int tx) __attribute__((always_inline)) {
           float nt[4];
@@ -259,6 +304,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
           return 0;
         },
         [&](int, int) __attribute__((always_inline)) {});
+  });
 
   // ---- bound: lane-wise merge of the S waves' lists, then the K-th over the 16 lanes
   {
@@ -281,6 +327,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
   sel.bound_finish();
 
   // ---- sweep 2: select
+  over_slabs([&]() __attribute__((always_inline)) {
   sweep(qy_lo + wave, S,
         [&](const f4& acc, float X, float Y, int tx) __attribute__((always_inline)) {
           float nt[4];
@@ -300,6 +347,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
           return a;
         },
         [&](const Admit& a, int jg) __attribute__((always_inline)) { sel.commit(a, jg); });
+  });
   sel.flush();
 
   // ---- exact merge of the S waves' lists: reference column v is finished by wave v mod S,
@@ -348,9 +396,59 @@ xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
 typedef void (*XcFastKernel)(const float*, const float*, const float*, const float*, int*,
                              float*, const FastGeom);
 
+// 3D search over a volume: one workgroup per (reference depth z, 4 x 4 reference block),
+// XCD-aware order over both.  Norm maps (and max maps) of every slab are stacked by depth;
+// outputs are stacked by reference depth.
+template <class CT, int C, int KR, int NT>
+__global__ void __launch_bounds__(64 * fast_max_waves(CT::kSplit ? 1 : 0, C))
+xcorr_topk_depth(const float* __restrict__ vol, const float* __restrict__ nrm,
+                 const float* __restrict__ amax, int* __restrict__ out_idx,
+                 float* __restrict__ out_dist, const FastGeom g, const DepthGeom dg) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int t = xcd_remap(blockIdx.x, g.nwg_total * dg.Z);
+  const int z = t / g.nwg_total;
+  const int blk = t - z * g.nwg_total;
+  const size_t slab = (size_t)g.H * g.W, nslab = (size_t)g.Hv * g.Wv;
+  const size_t outs = (size_t)g.nry * g.nrx * g.K;
+  const int lo = z - dg.before;
+  const DepthWin dw{vol, nrm, amax, max(0, lo), min(dg.Z - 1, lo + dg.c - 1), dg.tiles};
+  fast_block<CT, C, KR, NT, true>(vol + z * slab, nrm + z * nslab, nullptr,
+                                  amax ? amax + (size_t)z * dg.tiles : nullptr,
+                                  out_idx + z * outs, out_dist + z * outs, g, blk, lds, &dw);
+}
+
+typedef void (*XcDepthKernel)(const float*, const float*, const float*, int*, float*,
+                              const FastGeom, const DepthGeom);
+
 // policy for (precision, C, H2): 0 float32, 1 bfloat16 split, 2 float16 split
 template <int PREC, int C, int H2>
 using CtFor = std::conditional_t<PREC == 0, CtF32<C, H2>, CtSplit<C, H2, PREC == 2>>;
+
+template <int PREC, int C, int H2, int KR>
+static XcDepthKernel depth_nt(int nt) {
+  if constexpr (PREC != 0 && H2 < 3) {
+    return nullptr;
+  } else {
+    switch (nt) {
+      case 2: return xcorr_topk_depth<CtFor<PREC, C, H2>, C, KR, 2>;
+      case 3: return xcorr_topk_depth<CtFor<PREC, C, H2>, C, KR, 3>;
+    }
+    return nullptr;
+  }
+}
+
+template <int PREC, int C>
+static XcDepthKernel depth_h2(int h2, int kr, int nt) {
+  switch (h2 * 4 + kr) {
+    case 2 * 4 + 1: return depth_nt<PREC, C, 2, 1>(nt);
+    case 2 * 4 + 2: return depth_nt<PREC, C, 2, 2>(nt);
+    case 3 * 4 + 1: return depth_nt<PREC, C, 3, 1>(nt);
+    case 3 * 4 + 2: return depth_nt<PREC, C, 3, 2>(nt);
+    case 4 * 4 + 1: return depth_nt<PREC, C, 4, 1>(nt);
+    case 4 * 4 + 2: return depth_nt<PREC, C, 4, 2>(nt);
+  }
+  return nullptr;
+}
 
 template <int PREC, int C, int H2, int KR>
 static XcFastKernel fast_nt(int nt) {

@@ -172,6 +172,63 @@ def rgbnir1024() -> Workload:
                     {"field": "voronoi base x gain (3 ch) + base+smooth (NIR)", "sigma255": 30})
 
 
+# --------------------------------------------------------------------------------------
+# Volumes for the 3D search (Sec. IV, 3D Self-Convolution; the multi-channel runtime
+# setups of Sec. V-A: video frames searched across 9 frames, multi-modality data across 2)
+# --------------------------------------------------------------------------------------
+@dataclass(frozen=True)
+class BMShape3D:
+    """A 3D search: q planes of H x W, d x P x P blocks, Wn x Wn x c windows."""
+
+    height: int
+    width: int
+    planes: int
+    patch: int
+    patch_depth: int
+    stride: int
+    window: int
+    window_depth: int
+    k: int
+
+    @property
+    def n_ref(self) -> int:
+        return (self.planes - self.patch_depth + 1) * (
+            (self.height - self.patch) // self.stride + 1) * ((self.width - self.patch) // self.stride + 1)
+
+
+def video_voronoi(seed: int, q: int, H: int, W: int, sigma255: float,
+                  motion=(1, 2)) -> np.ndarray:
+    """q frames of a Voronoi scene translated by ``motion`` pixels per frame (circularly),
+    plus independent noise per frame; q x H x W float32.
+
+    Draw order: the Voronoi base, then the noise (frame-major)."""
+    rng = np.random.default_rng(seed)
+    base = voronoi_field(rng, H, W)
+    dy, dx = motion
+    vol = np.stack([np.roll(base, (t * dy, t * dx), axis=(0, 1)) for t in range(q)])
+    vol = vol + _noise(rng, vol.shape, sigma255)
+    return vol.astype(np.float32)
+
+
+# paper: 256 x 256 x q, 6 x 6 x d patches, stride 1, 30 x 30 x c windows (the centred
+# window takes an odd side: 31)
+SHAPE_VIDEO = BMShape3D(256, 256, 20, 6, 1, 1, 31, 9, 16)
+SHAPE_MULTIMODAL = BMShape3D(256, 256, 6, 6, 3, 1, 31, 2, 16)
+
+
+def video20() -> Workload:
+    """20 frames of 256 x 256, 6 x 6 x 1 blocks searched over 31 x 31 x 9 (seed 3)."""
+    return Workload("video20_3d", SHAPE_VIDEO, video_voronoi(3, 20, 256, 256, 25.0), 3,
+                    {"field": "voronoi 64 seeds moving (1, 2) px per frame", "sigma255": 25})
+
+
+def multimodal6() -> Workload:
+    """6 correlated planes of 256 x 256, 6 x 6 x 3 blocks searched over 31 x 31 x 2 (seed 4)."""
+    return Workload("multimodal6_3d", SHAPE_MULTIMODAL,
+                    multichannel_voronoi(4, 256, 256, 6, 25.0), 4,
+                    {"field": "voronoi base x gain U[0.7, 1.3] per plane", "sigma255": 25})
+
+
 def uneven_batch(n_images: int = 64, seed0: int = 1000):
     """Batch of images with independent random sides in [128, 1024], C in {1,3}, P in {6,8}.
 

@@ -34,13 +34,53 @@ class ParityReport:
                 "tolerant_set_mismatch": self.tolerant_mismatch, "order_violations": self.order_violations}
 
 
+def _check_row(rep, i, d, j, K, gi, gd, ni, norm_of, tol, floor):
+    """One GPU row against the oracle's in-window distances d (indices j) of reference i;
+    ni is the reference's oracle norm, norm_of(j) a candidate's."""
+    ncand = d.size
+    oidx, odist = O.select_k(d, j, K)
+    lookup = dict(zip(j.tolist(), d.tolist()))
+    rep.n_refs += 1
+    kk = min(K, ncand)
+    # padding
+    if np.any(gi[kk:] != -1) or np.any(np.isfinite(gd[kk:])):
+        rep.tolerant_mismatch += 1
+        rep.messages.append(f"ref {i}: bad padding")
+        return
+    members = gi[:kk].tolist()
+    if len(set(members)) != kk or any(m not in lookup for m in members):
+        rep.tolerant_mismatch += 1
+        rep.messages.append(f"ref {i}: non-candidate or duplicate indices {members}")
+        return
+    dstar = np.array([lookup[m] for m in members])
+    nj = np.array([norm_of(m) for m in members])
+    rel = np.abs(gd[:kk].astype(np.float64) - dstar) / np.maximum(dstar, floor * (ni + nj))
+    rep.rel.append(rel)
+    if np.any(rel > tol):
+        rep.tolerant_mismatch += 1
+        rep.messages.append(f"ref {i}: rel error {rel.max():.3e}")
+    # ascending order of the GPU's own keys
+    keys = list(zip(gd[:kk].tolist(), members))
+    if keys != sorted(keys):
+        rep.order_violations += 1
+    # set rule
+    t = odist[kk - 1]
+    jk = int(oidx[kk - 1])
+    tau = tol * max(t, floor * (ni + norm_of(jk)))
+    if set(members) != set(oidx[:kk].tolist()):
+        rep.strict_mismatch += 1
+        must = {int(a) for a, b in zip(j, d) if b < t - tau}
+        if np.any(dstar > t + tau) or not must.issubset(set(members)):
+            rep.tolerant_mismatch += 1
+            rep.messages.append(f"ref {i}: set rule violated")
+
+
 def check(x, P, s, Wn, K, gpu_idx, gpu_dist, refs=None, tol=1e-4, floor=1e-2, report=None):
     """Check GPU rows (for reference numbers ``refs``, default all) against the oracle."""
     x64 = np.asarray(x, dtype=np.float64)
     if x64.ndim == 2:
         x64 = x64[None]
     C, H, W = x64.shape
-    Hv, Wv = H - P + 1, W - P + 1
     N = O.patch_norms(x64, P)
     rl = O.ref_list(H, W, P, s)
     sel = np.arange(len(rl)) if refs is None else np.asarray(refs)
@@ -50,45 +90,36 @@ def check(x, P, s, Wn, K, gpu_idx, gpu_dist, refs=None, tol=1e-4, floor=1e-2, re
     for row, i in enumerate(sel):
         ry, rx = int(rl[i, 0]), int(rl[i, 1])
         d, j = O.window_distances(x64, P, Wn, ry, rx)
-        ncand = d.size
-        oidx, odist = O.select_k(d, j, K)
-        lookup = dict(zip(j.tolist(), d.tolist()))
-        gi = gpu_idx[row]
-        gd = gpu_dist[row]
-        rep.n_refs += 1
-        kk = min(K, ncand)
-        # padding
-        if np.any(gi[kk:] != -1) or np.any(np.isfinite(gd[kk:])):
-            rep.tolerant_mismatch += 1
-            rep.messages.append(f"ref {i}: bad padding")
-            continue
-        members = gi[:kk].tolist()
-        if len(set(members)) != kk or any(m not in lookup for m in members):
-            rep.tolerant_mismatch += 1
-            rep.messages.append(f"ref {i}: non-candidate or duplicate indices {members}")
-            continue
-        dstar = np.array([lookup[m] for m in members])
-        ni = N[ry, rx]
-        nj = np.array([N[m // W, m % W] for m in members])
-        rel = np.abs(gd[:kk].astype(np.float64) - dstar) / np.maximum(dstar, floor * (ni + nj))
-        rep.rel.append(rel)
-        if np.any(rel > tol):
-            rep.tolerant_mismatch += 1
-            rep.messages.append(f"ref {i}: rel error {rel.max():.3e}")
-        # ascending order of the GPU's own keys
-        keys = list(zip(gd[:kk].tolist(), members))
-        if keys != sorted(keys):
-            rep.order_violations += 1
-        # set rule
-        t = odist[kk - 1]
-        jk = int(oidx[kk - 1])
-        tau = tol * max(t, floor * (ni + N[jk // W, jk % W]))
-        if set(members) != set(oidx[:kk].tolist()):
-            rep.strict_mismatch += 1
-            must = {int(a) for a, b in zip(j, d) if b < t - tau}
-            if np.any(dstar > t + tau) or not must.issubset(set(members)):
-                rep.tolerant_mismatch += 1
-                rep.messages.append(f"ref {i}: set rule violated")
+        _check_row(rep, i, d, j, K, gpu_idx[row], gpu_dist[row], N[ry, rx],
+                   lambda m: N[m // W, m % W], tol, floor)
+    return rep
+
+
+def check3d(v, P, d, s, Wn, c, K, gpu_idx, gpu_dist, refs=None, tol=1e-4, floor=1e-2,
+            report=None):
+    """3D search: the same rules with the oracle's 3D window (references depth-major,
+    indices volume positions) and per-slab norms."""
+    v64 = np.asarray(v, dtype=np.float64)
+    q, H, W = v64.shape
+    Z = q - d + 1
+    N = np.stack([O.patch_norms(v64[z:z + d], P) for z in range(Z)])
+    rl = O.ref_list(H, W, P, s)
+    n2 = len(rl)
+    sel = np.arange(Z * n2) if refs is None else np.asarray(refs)
+    gpu_idx = np.asarray(gpu_idx)
+    gpu_dist = np.asarray(gpu_dist)
+    rep = report or ParityReport()
+
+    def norm_of(m):
+        zc, rem = divmod(int(m), H * W)
+        return N[zc, rem // W, rem % W]
+
+    for row, i in enumerate(sel):
+        z, i2 = divmod(int(i), n2)
+        ry, rx = int(rl[i2, 0]), int(rl[i2, 1])
+        dd, jj = O.window3d_distances(v64, P, d, Wn, c, z, ry, rx)
+        _check_row(rep, i, dd, jj, K, gpu_idx[row], gpu_dist[row], N[z, ry, rx], norm_of, tol,
+                   floor)
     return rep
 
 

@@ -136,3 +136,35 @@ def test_group_arguments_checked_on_host():
     assert lib.bm_aggregate(None, None, None, None, None, None) == bm.BM_EINVAL
     out = C.c_int64()
     assert lib.bm_aggregate_workspace(None, C.byref(out)) == bm.BM_EINVAL
+
+
+@pytest.mark.parametrize("pd,wd,channels,status,needle", [
+    (1, 0, 4, "BM_EINVAL", "window_depth"), (0, 3, 4, "BM_EINVAL", "patch_depth"),
+    (5, 3, 4, "BM_EINVAL", "patch_depth"), (2, -1, 4, "BM_EINVAL", "window_depth"),
+    (5, 2, 8, "BM_ENOTSUP", "patch_depth <= 4"), (2, 3, 70000, "BM_EINVAL", "volume planes"),
+])
+def test_3d_descriptors_checked_on_host(pd, wd, channels, status, needle):
+    """3D fields: both 0 (2D) or window_depth >= 1 with 1 <= patch_depth <= channels; the
+    kernels take patch_depth <= 4."""
+    bm = ensure_built()
+    d = bm.make_desc(8, 8, channels, 3, 1, 3, 4, "fp32", 0, pd, wd)
+    with pytest.raises(bm.BMError) as ei:
+        bm.bm_plan(d)
+    assert ei.value.status == getattr(bm, status)
+    assert needle in str(ei.value)
+
+
+@pytest.mark.parametrize("flags", [1, 2])
+def test_3d_takes_no_flags(flags):
+    bm = ensure_built()
+    with pytest.raises(bm.BMError) as ei:
+        bm.bm_plan(bm.make_desc(64, 64, 6, 6, 2, 15, 16, "fp32", flags, 2, 3))
+    assert ei.value.status == bm.BM_ENOTSUP
+
+
+def test_3d_descriptor_layout():
+    """The two depth fields follow flags in the C struct (9 + 2 int32 fields)."""
+    bm = ensure_built()
+    import ctypes as C
+    assert C.sizeof(bm.bm_desc) == 44
+    assert bm.bm_desc.patch_depth.offset == 36 and bm.bm_desc.window_depth.offset == 40

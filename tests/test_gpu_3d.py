@@ -1,0 +1,188 @@
+"""GPU parity of the 3D search (window_depth > 0; Sec. IV, 3D Self-Convolution) against the
+FP64 oracle, through the C ABI (bm_plan / bm_match / bm_norms / bm_cross_topk).
+
+Distances follow the tolerance rule of the 2D tests (float32 and float16 split: 1e-4
+relative with the norm floor; bfloat16 split: 2e-3), index sets follow the set rule.
+Reductions that must hold bit for bit: a one-slab window with d = q is the 2D kernel on the
+same image, and a one-slab window with d < q is the 2D kernel on each slab.
+"""
+import numpy as np
+import pytest
+
+from oracle import bm_oracle as O
+from paper_2006_13714_amd import synth
+from tests import parity
+from tests.libutil import banner, ensure_built
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-4, "fp16x3": 1e-4, "bf16x3": 2e-3}
+
+
+def run3d(v, P, d, s, Wn, c, K, precision="fp32"):
+    import torch
+    bm = ensure_built()
+    t = torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).cuda()
+    idx, dist = bm.match3d(t, P, d, s, Wn, c, K, precision=precision)
+    torch.cuda.synchronize()
+    return idx.cpu().numpy(), dist.cpu().numpy()
+
+
+def assert_parity(v, P, d, s, Wn, c, K, idx, dist, precision, refs=None):
+    if refs is not None:
+        idx, dist = idx[refs], dist[refs]
+    rep = parity.check3d(v, P, d, s, Wn, c, K, idx, dist, refs=refs, tol=TOL[precision])
+    assert rep.tolerant_mismatch == 0, (rep.summary(), rep.messages[:4])
+    assert rep.order_violations == 0, rep.summary()
+    return rep.summary()
+
+
+@pytest.mark.parametrize("seed,q,H,W,P,d,s,Wn,c,K", [
+    (1, 5, 40, 44, 6, 1, 2, 15, 3, 16), (2, 6, 36, 33, 5, 3, 3, 13, 2, 8),
+    (3, 4, 30, 35, 8, 2, 1, 17, 4, 20), (4, 7, 29, 31, 3, 4, 2, 21, 9, 32),
+    (5, 3, 26, 23, 4, 3, 2, 13, 1, 12)])
+def test_small_volumes_fp32(gpu, seed, q, H, W, P, d, s, Wn, c, K):
+    banner(f"3d fp32 seed={seed} q={q} H={H} W={W} P={P} d={d} s={s} Wn={Wn} c={c} K={K}")
+    v = np.random.default_rng(seed).uniform(0.0, 1.0, size=(q, H, W)).astype(np.float32)
+    idx, dist = run3d(v, P, d, s, Wn, c, K)
+    assert idx.shape == ((q - d + 1) * len(O.ref_list(H, W, P, s)), K)
+    print(assert_parity(v, P, d, s, Wn, c, K, idx, dist, "fp32"))
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
+@pytest.mark.parametrize("seed,q,H,W,P,d,s,Wn,c,K", [
+    (6, 5, 38, 41, 6, 1, 2, 15, 3, 16), (7, 6, 34, 30, 8, 2, 3, 13, 2, 24)])
+def test_small_volumes_split(gpu, precision, seed, q, H, W, P, d, s, Wn, c, K):
+    banner(f"3d {precision} seed={seed} q={q} P={P} d={d} c={c}")
+    v = synth.video_voronoi(seed, q, H, W, 25.0, motion=(1, -1))
+    idx, dist = run3d(v, P, d, s, Wn, c, K, precision)
+    print(assert_parity(v, P, d, s, Wn, c, K, idx, dist, precision))
+
+
+def _sample(Z, n2, nrx, n_mid, seed):
+    rng = np.random.default_rng(seed)
+    edge = []
+    for z in (0, Z // 2, Z - 1):
+        edge += [z * n2, z * n2 + nrx - 1, z * n2 + n2 - nrx, z * n2 + n2 - 1]
+    return np.unique(np.concatenate([edge, rng.choice(Z * n2, n_mid, replace=False)]))
+
+
+@pytest.mark.parametrize("workload,precision", [("video20", "fp32"), ("video20", "fp16x3"),
+                                                ("multimodal6", "fp32"), ("multimodal6", "bf16x3")])
+def test_full_size_sampled(gpu, workload, precision):
+    """The full-size volumes in the launch configuration the benchmark times; sampled
+    references (every corner of the first, middle and last depth plus random ones)."""
+    w = getattr(synth, workload)()
+    sh = w.shape
+    banner(f"3d full {workload} {precision}")
+    idx, dist = run3d(w.image, sh.patch, sh.patch_depth, sh.stride, sh.window, sh.window_depth,
+                      sh.k, precision)
+    Z = sh.planes - sh.patch_depth + 1
+    nrx = (sh.width - sh.patch) // sh.stride + 1
+    n2 = nrx * ((sh.height - sh.patch) // sh.stride + 1)
+    assert idx.shape == (sh.n_ref, sh.k)
+    refs = _sample(Z, n2, nrx, 150, 21)
+    print(assert_parity(w.image, sh.patch, sh.patch_depth, sh.stride, sh.window,
+                        sh.window_depth, sh.k, idx, dist, precision, refs))
+
+
+def test_motion_is_recovered_exactly(gpu):
+    """Noise-free frames that are shifted copies: for interior references the three
+    zero-distance blocks (the reference and its copies one frame ahead and behind) lead
+    every list, in index order."""
+    banner("3d motion")
+    rng = np.random.default_rng(9)
+    q, H, W, P, dy, dx = 6, 48, 52, 6, 1, 2
+    f0 = np.round(rng.uniform(0, 8, size=(H, W)))  # small integers: float32 sums are exact
+    v = np.stack([np.roll(f0, (t * dy, t * dx), axis=(0, 1)) for t in range(q)]).astype(np.float32)
+    idx, dist = run3d(v, P, 1, 3, 15, 3, 8)
+    rl = O.ref_list(H, W, P, 3)
+    n2 = len(rl)
+    checked = 0
+    for z in range(1, q - 1):
+        for i2, (ry, rx) in enumerate(rl):
+            if not (8 <= ry < H - P - 8 and 8 <= rx < W - P - 8):
+                continue
+            want = sorted([(z * H + ry) * W + rx, ((z + 1) * H + ry + dy) * W + rx + dx,
+                           ((z - 1) * H + ry - dy) * W + rx - dx])
+            n = z * n2 + i2
+            assert idx[n, :3].tolist() == want
+            assert np.all(dist[n, :3] == 0) and dist[n, 3] > 0
+            checked += 1
+    assert checked > 50
+
+
+def test_one_slab_windows_are_the_2d_kernel(gpu):
+    import torch
+    bm = ensure_built()
+    banner("3d c=1 reductions")
+    rng = np.random.default_rng(10)
+    q, H, W, P, s, Wn, K = 5, 45, 50, 6, 2, 17, 16
+    v = rng.uniform(size=(q, H, W)).astype(np.float32)
+    t = torch.from_numpy(v).cuda()
+    # d = q: the plain multi-channel problem
+    i3, d3 = bm.match3d(t[:4].contiguous(), P, 4, s, Wn, 1, K)
+    i2, d2 = bm.match(t[:4].contiguous(), P, s, Wn, K)
+    torch.cuda.synchronize()
+    assert torch.equal(i3, i2) and torch.equal(d3.view(torch.int32), d2.view(torch.int32))
+    # d < q: slab by slab, indices offset by z H W
+    d_ = 2
+    i3, d3 = bm.match3d(t, P, d_, s, Wn, 1, K)
+    n2 = len(O.ref_list(H, W, P, s))
+    for z in range(q - d_ + 1):
+        i2, d2 = bm.match(t[z:z + d_].contiguous(), P, s, Wn, K)
+        torch.cuda.synchronize()
+        exp = torch.where(i2 >= 0, i2 + z * H * W, i2)
+        assert torch.equal(i3[z * n2:(z + 1) * n2], exp)
+        assert torch.equal(d3[z * n2:(z + 1) * n2].view(torch.int32), d2.view(torch.int32))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16x3"])
+def test_stage_calls_equal_match(gpu, precision):
+    """bm_norms writes one norm map per slab; with bm_cross_topk it reproduces bm_match."""
+    import torch
+    bm = ensure_built()
+    banner(f"3d stages {precision}")
+    v = synth.video_voronoi(11, 6, 40, 37, 25.0)
+    q, H, W = v.shape
+    P, d, s, Wn, c, K = 6, 2, 2, 15, 3, 16
+    plan = bm.bm_plan(bm.make_desc(H, W, q, P, s, Wn, K, precision, 0, d, c))
+    t = torch.from_numpy(v).cuda()
+    Z = q - d + 1
+    Hv, Wv = H - P + 1, W - P + 1
+    nrm = torch.empty((Z, Hv, Wv), dtype=torch.float32, device="cuda")
+    bm.bm_norms(plan, t, nrm)
+    i1 = torch.empty((plan.n_ref, K), dtype=torch.int32, device="cuda")
+    d1 = torch.empty((plan.n_ref, K), dtype=torch.float32, device="cuda")
+    bm.bm_cross_topk(plan, t, nrm, i1, d1)
+    i2 = torch.empty_like(i1)
+    d2 = torch.empty_like(d1)
+    bm.bm_match(plan, t, i2, d2)
+    torch.cuda.synchronize()
+    assert torch.equal(i1, i2) and torch.equal(d1.view(torch.int32), d2.view(torch.int32))
+    on = np.stack([O.patch_norms(v[z:z + d], P) for z in range(Z)])
+    np.testing.assert_allclose(nrm.cpu().numpy(), on, rtol=2e-6, atol=1e-6)
+
+
+def test_unsupported_uses_of_3d_plans(gpu):
+    import torch
+    bm = ensure_built()
+    banner("3d errors")
+    x = torch.zeros((6, 64, 64), dtype=torch.float32, device="cuda")
+    plan = bm.bm_plan(bm.make_desc(64, 64, 6, 6, 2, 15, 16, "fp32", 0, 2, 3))
+    assert plan.n_ref == 5 * 30 * 30
+    idx = torch.zeros((plan.n_ref, 16), dtype=torch.int32, device="cuda")
+    g = torch.empty((plan.n_ref * 16 * 2 * 36,), dtype=torch.float32, device="cuda")
+    calls = [lambda: bm.bm_gather(plan, x, idx, g),
+             lambda: bm.bm_aggregate_workspace(plan),
+             lambda: bm.bm_nlm(plan, x, 1.0, g),
+             lambda: bm.bm_batch_workspace([plan])]
+    for call in calls:
+        with pytest.raises(bm.BMError) as ei:
+            call()
+        assert ei.value.status == bm.BM_ENOTSUP
+    # outside the specialised kernel's envelope: patch 10, or a 47-wide window at stride 1
+    for P, Wn in ((10, 15), (6, 47)):
+        with pytest.raises(bm.BMError) as ei:
+            bm.bm_plan(bm.make_desc(64, 64, 6, P, 1, Wn, 16, "fp32", 0, 2, 3))
+        assert ei.value.status == bm.BM_ENOTSUP
