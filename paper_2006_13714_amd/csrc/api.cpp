@@ -160,6 +160,7 @@ hipError_t launch_nlm(const float* img, const float* nrm, float* patch, float* t
 hipError_t launch_gather(const float* img, const int32_t* idx, float* groups, const GroupGeom& g,
                          hipStream_t s);
 long long aggregate_workspace_bytes(const GroupGeom& g);
+void aggregate_tiling(GroupGeom& g);
 hipError_t launch_aggregate(const float* groups, const int32_t* idx, float* out, void* ws,
                             const GroupGeom& g, hipStream_t s);
 
@@ -177,6 +178,11 @@ static GroupGeom group_geom(const bm_plan_s& p) {
   int bits = 0;
   while ((1ll << bits) < n) ++bits;
   g.cnt_bits = bits;
+  g.s = p.geom.s;
+  g.r = p.geom.r;
+  g.nry = p.geom.nry;
+  g.nrx = p.geom.nrx;
+  aggregate_tiling(g);
   return g;
 }
 }  // namespace bmk

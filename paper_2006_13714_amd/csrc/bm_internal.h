@@ -46,14 +46,14 @@ struct XcGeom {
   int metric;           // 0 Euclidean, 1 normalized cross-correlation
 };
 
-// The fields of XcGeom that the specialised kernel reads (kernel argument of the
-// single-image launch; per-image record of the batch launch).
 // 3D search: Z = q - d + 1 slabs (reference depths), the depth window holds depths
 // z - before .. z - before + c - 1 (clipped to 0..Z-1), `tiles` max-map entries per slab.
 struct DepthGeom {
   int Z, before, c, tiles;
 };
 
+// The fields of XcGeom that the specialised kernel reads (kernel argument of the
+// single-image launch; per-image record of the batch launch).
 struct FastGeom {
   int H, W, Hv, Wv, P, s, r, K;
   int nry, nrx, nwg_x, nwg_total;
@@ -102,6 +102,10 @@ struct GroupGeom {
   int C, H, W, P, Hv, Wv, K;
   long long n_ref;
   int cnt_bits;  // ceil(log2(n_ref * K + 1)): headroom of the fixed-point sums
+  int s, r, nry, nrx;  // reference grid and window half-width of the plan
+  // aggregation tiles: tb x tb references per workgroup, whose windows cover a region of
+  // th x tw pixels accumulated in LDS (tb = 0: no tiling)
+  int tb, th, tw, ntx, nty;
 };
 
 // Per-image outputs of the norm pass that the cross-term pass reads besides the norm map:

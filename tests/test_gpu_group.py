@@ -109,3 +109,29 @@ def test_aggregate_is_bitwise_deterministic(gpu):
     a = aggregate(groups, idx, (C, H, W), P, s, Wn, K)
     b = aggregate(groups, idx, (C, H, W), P, s, Wn, K)
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+@pytest.mark.parametrize("C,H,W,P,s,Wn,K", [(2, 50, 47, 6, 2, 13, 10),   # 4 x 4 reference tiles
+                                             (1, 110, 116, 8, 3, 85, 6)])  # region too big: untiled
+def test_aggregate_indices_anywhere(gpu, C, H, W, P, s, Wn, K):
+    """Valid positions anywhere in the image (not window members): deposits outside a tile's
+    LDS region take the direct route; a window too large for a tile region uses the untiled
+    kernel.  Both against the oracle, and bitwise repeatable."""
+    banner(f"group aggregate anywhere C={C} H={H} W={W} P={P} s={s} Wn={Wn} K={K}")
+    rng = np.random.default_rng(C * 7 + Wn)
+    Hv, Wv = H - P + 1, W - P + 1
+    n_ref = len(O.ref_list(H, W, P, s))
+    qy = rng.integers(0, Hv, size=(n_ref, K))
+    qx = rng.integers(0, Wv, size=(n_ref, K))
+    idx = (qy * W + qx).astype(np.int32)
+    idx[rng.random(idx.shape) < 0.05] = -1
+    groups = rng.uniform(-2.0, 5.0, size=(n_ref, K, C, P, P)).astype(np.float32)
+    out = aggregate(groups, idx, (C, H, W), P, s, Wn, K)
+    oo, _ = O.aggregate_groups(groups.astype(np.float64), idx.astype(np.int64), C, H, W)
+    tol = 2 * np.finfo(np.float32).eps * np.abs(groups).max()
+    assert np.max(np.abs(out - oo)) <= tol
+    again = aggregate(groups, idx, (C, H, W), P, s, Wn, K)
+    assert np.array_equal(out.view(np.uint32), again.view(np.uint32))
+    g = gather(out, idx, P, s, Wn, K)
+    og = O.gather_groups(out, idx.astype(np.int64), P)
+    assert np.array_equal(g.reshape(og.shape), og.astype(np.float32))
