@@ -140,7 +140,7 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) 
   int buf_bytes = nw * 16 * cap * 8;
   if (fast) {
     const int kr = d.k <= 16 ? 1 : 2;
-    const int tl_bytes = nw * 4 * (2 * kr) * 64 * 4;   // bounding-list exchange
+    const int tl_bytes = nw * 4 * (2 * kr) * 64 * 4 + 4 * 64 * 4;  // bounding lists + bounds
     const int list_bytes = nw * 4 * kr * 64 * 8;        // final-list exchange
     buf_bytes = buf_bytes > tl_bytes ? buf_bytes : tl_bytes;
     buf_bytes = buf_bytes > list_bytes ? buf_bytes : list_bytes;

@@ -94,17 +94,15 @@ struct RefSelect {
     for (int v = 0; v < 4; ++v) lane_insert<TL>(tl[v], inw[v] ? dist(acc, nc, v) : INFINITY);
   }
 
-  __device__ __forceinline__ void bound_finish() {
+  // threshold of reference column v from its (all-wave) lane lists
+  __device__ __forceinline__ void bound_finish_col(int v) {
+    float L[KR];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      float L[KR];
+    for (int q = 0; q < KR; ++q) L[q] = INFINITY;
 #pragma unroll
-      for (int q = 0; q < KR; ++q) L[q] = INFINITY;
-#pragma unroll
-      for (int i = 0; i < TL; ++i) merge_batch_d<KR>(L, tl[v][i], p16);
-      // a strict "<" against the next float up admits exactly d <= bound
-      th[v] = fminf(th[v], next_up(kth_distance<KR>(L, K)));
-    }
+    for (int i = 0; i < TL; ++i) merge_batch_d<KR>(L, tl[v][i], p16);
+    // a strict "<" against the next float up admits exactly d <= bound
+    th[v] = fminf(th[v], next_up(kth_distance<KR>(L, K)));
   }
 
   // ---- sweep 2

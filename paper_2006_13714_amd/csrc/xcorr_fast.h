@@ -306,25 +306,34 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
         [&](int, int) __attribute__((always_inline)) {});
   });
 
-  // ---- bound: lane-wise merge of the S waves' lists, then the K-th over the 16 lanes
+  // ---- bound: wave w finishes the reference columns v with v % S == w: it merges the
+  //      other waves' lane lists for that column into its own, takes the K-th over the 16
+  //      lanes of each group, and publishes the thresholds; every wave then reads all four
   {
     float* tlx = reinterpret_cast<float*>(buf_all);  // [S][4][TL][64]
+    float* thx = tlx + S * 4 * TL * 64;              // [4][64]
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int i2 = 0; i2 < TL; ++i2) tlx[((wave * 4 + v) * TL + i2) * 64 + lane] = sel.tl[v][i2];
     __syncthreads();
-    for (int w = 0; w < S; ++w) {
-      if (w == wave) continue;
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < 4; ++v) {
+      if ((v % S) != wave) continue;
+      for (int w = 0; w < S; ++w) {
+        if (w == wave) continue;
 #pragma unroll
         for (int i2 = 0; i2 < TL; ++i2)
           lane_insert<TL>(sel.tl[v], tlx[((w * 4 + v) * TL + i2) * 64 + lane]);
+      }
+      sel.bound_finish_col(v);
+      thx[v * 64 + lane] = sel.th[v];
     }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sel.th[v] = thx[v * 64 + lane];
     __syncthreads();  // the exchange area is the candidate buffers
   }
-  sel.bound_finish();
 
   // ---- sweep 2: select
   over_slabs([&]() __attribute__((always_inline)) {
