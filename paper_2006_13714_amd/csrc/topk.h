@@ -44,12 +44,16 @@ __device__ __forceinline__ bool key_less(float ad, int aj, float bd, int bj) {
   return (ad < bd) | ((ad == bd) & (aj < bj));
 }
 
-// Compare-exchange with the lane at xor distance M inside a 16-lane row.
+// Compare-exchange with the lane at xor distance M inside a 16-lane row.  The two keys are
+// distinct or the two entries are identical (j is unique per reference; padding entries are
+// all (+inf, INT_MAX)), so "keep the smaller" takes the partner exactly when the partner's
+// key is smaller, and "keep the larger" exactly when it is not: one comparison chain and a
+// mask comparison instead of two chains and a select between them.
 template <int M>
 __device__ __forceinline__ void cmpx(float& d, int& j, bool keep_min) {
   const float pd = xor_lane<M>(d);
   const int pj = xor_lane<M>(j);
-  const bool take = keep_min ? key_less(pd, pj, d, j) : key_less(d, j, pd, pj);
+  const bool take = key_less(pd, pj, d, j) == keep_min;
   d = take ? pd : d;
   j = take ? pj : j;
 }
@@ -118,10 +122,12 @@ __device__ __forceinline__ void merge_batch(float (&Ld)[KR], int (&Lj)[KR], floa
 }
 
 // ---- distance-only networks (no indices): used to bound the K-th distance ------------
+// Distances only: min or max by a compare and a select (no NaN ever reaches these networks,
+// so the min/max of the IEEE functions and their operand canonicalisation are not needed).
 template <int M>
 __device__ __forceinline__ void cmpx_d(float& d, bool keep_min) {
   const float pd = xor_lane<M>(d);
-  d = keep_min ? fminf(d, pd) : fmaxf(d, pd);
+  d = ((pd < d) == keep_min) ? pd : d;
 }
 
 template <int K, int M>
