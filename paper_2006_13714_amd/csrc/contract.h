@@ -4,8 +4,8 @@
 // Both policies compute, for a tile of 16 references x 16 candidates, the cross terms
 // <X_i, X_j> of Eq. (eq:selfConv) summed over channels (Sec. IV, S(.)), with a float32
 // accumulator.  The strip in LDS holds one image row per channel in consecutive strip rows
-// of RW 32-bit words; a tile's operand-B reads are one base register plus compile-time
-// immediate offsets.
+// of RW 32-bit words; a tile's operand-B reads are one base register (two for the split
+// forms: hi and lo planes) plus compile-time immediate offsets.
 //
 //  CtF32   float32 products, v_mfma_f32_16x16x4f32; a step covers a 2 x 2 pixel block of one
 //          channel (lane group g holds pixel (g/2, g%2) of the block).
@@ -13,7 +13,10 @@
 //          pre-scale (FP16 = true); three products hi*hi + hi*lo + lo*hi per element on
 //          v_mfma_f32_16x16x32_{bf16,f16}.  A lane holds a 4-row x 2-column pixel block per
 //          32-element block; the strip stores, per pixel x, the 32-bit word (v[x], v[x+1])
-//          of 16-bit parts (rows: channel, then part hi/lo), so every read is aligned.
+//          of 16-bit parts, so every read is aligned.  The hi parts form one plane (rows:
+//          image row, then channel) and the lo parts a second plane SH * C rows later, so the
+//          four rows of an operand pair up into two-word reads of one plane and land in the
+//          matrix op's operand registers without copies.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,6 +42,7 @@ struct CtF32 {
   static constexpr bool kScaled = false;
   static constexpr bool kSplit = false;
   using AReg = float;
+  using BReg = float;                          // one operand B per matrix op
 
   // step t = ((l2 * H2) + m2) * C + c: pixels (2*l2 + dy, 2*m2 + dx), dy, dx in {0,1}
   static constexpr int l2(int t) { return t / (H2 * C); }
@@ -47,6 +51,7 @@ struct CtF32 {
   static constexpr int off(int t) { return (2 * l2(t) * C + ch(t)) * RW + 2 * m2(t); }
 
   __device__ static int lane_off(int gp) { return (gp >> 1) * CRS + (gp & 1); }
+  __device__ static int plane_off(const FastGeom&) { return 0; }  // one plane
 
   // strip rows (y*C + c): the centred image values, zero outside the image
   __device__ static void stage(uint32_t* strip, const float* img, const FastGeom& g, int SY0,
@@ -69,7 +74,8 @@ struct CtF32 {
 
   // operand A for the reference whose patch starts at strip word `base` (lane offset
   // included); elements outside the P x P patch (odd P) are zero
-  __device__ static void load_a(AReg (&A)[NS], const uint32_t* strip, int base, int gp, int P) {
+  __device__ static void load_a(AReg (&A)[NS], const uint32_t* strip, int base, int gp, int P,
+                                int = 0) {
     const float* s = reinterpret_cast<const float*>(strip);
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
@@ -78,7 +84,7 @@ struct CtF32 {
     }
   }
 
-  __device__ static void load_b(float (&B)[NB], const uint32_t* strip, int base) {
+  __device__ static void load_b(float (&B)[NB], const uint32_t* strip, int base, int = 0) {
     const float* s = reinterpret_cast<const float*>(strip);
 #pragma unroll
     for (int t = 0; t < NB; ++t) B[t] = s[base + off(t)];
@@ -86,7 +92,7 @@ struct CtF32 {
 
   // the matrix-op chain with the next tile's reads interleaved; `nb` is their base
   __device__ static f4 chain_and_load(const AReg (&A)[NS], const float (&cur)[NB],
-                                      float (&nxt)[NB], const uint32_t* strip, int nb) {
+                                      float (&nxt)[NB], const uint32_t* strip, int nb, int = 0) {
     const float* s = reinterpret_cast<const float*>(strip);
     f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -130,28 +136,32 @@ __device__ __forceinline__ void split2(float v, uint32_t& hi, uint32_t& lo) {
 template <int C, int H2, bool FP16>
 struct CtSplit {
   static constexpr int RW = kSplitRW;
-  static constexpr int ROWS = 2 * C;          // per image row: channel c -> rows 2c (hi), 2c+1 (lo)
+  static constexpr int ROWS = C;              // per image row and plane: channel c -> row c
   static constexpr int CRS = ROWS * RW;
   static constexpr int PE = 2 * H2;
   static constexpr int NRB = (PE + 3) / 4;    // 4-row blocks
   static constexpr int NCB = (PE + 7) / 8;    // 8-column blocks
   static constexpr int NKB = C * NRB * NCB;   // 32-element blocks
   static constexpr int NS = 3 * NKB;          // matrix ops per tile
-  static constexpr int NB = 2 * 4 * NKB;      // operand-B words per tile (hi, lo)
+  static constexpr int NB = 2 * NKB;          // operand-B vectors per tile (hi, lo per block)
   static constexpr bool kScaled = FP16;
   static constexpr bool kSplit = true;
   using AReg = u4;                            // 8 x 16-bit parts
+  using BReg = u4;                            // held as whole 4-word vectors, so the reads
+                                              // land in the matrix op's operand registers
 
-  // block b = ((rb * NCB) + cb) * C + c; word (part, i) of block b: image row 4*rb + i,
-  // columns 8*cb + 2*g, +1 of channel c
+  // block b = ((rb * NCB) + cb) * C + c; word i of block b (in either plane): image row
+  // 4*rb + i, columns 8*cb + 2*g, +1 of channel c
   static constexpr int rb(int b) { return b / (NCB * C); }
   static constexpr int cb(int b) { return (b / C) % NCB; }
   static constexpr int ch(int b) { return b % C; }
-  static constexpr int woff(int b, int part, int i) {
-    return ((4 * rb(b) + i) * ROWS + 2 * ch(b) + part) * RW + 8 * cb(b);
+  static constexpr int woff(int b, int i) {
+    return ((4 * rb(b) + i) * ROWS + ch(b)) * RW + 8 * cb(b);
   }
 
   __device__ static int lane_off(int gp) { return 2 * gp; }
+  // words from the hi plane to the lo plane
+  __device__ static int plane_off(const FastGeom& g) { return g.SH * CRS; }
 
   __device__ static void stage(uint32_t* strip, const float* img, const FastGeom& g, int SY0,
                                int SX0, int first, int step, int lane, const float* center,
@@ -163,8 +173,8 @@ struct CtSplit {
       const bool yok = (iy >= 0) & (iy < g.H);
       const float cc = center[c];
       const float* src = img + ((size_t)c * g.H + (yok ? iy : 0)) * g.W;
-      uint32_t* dhi = strip + (y * ROWS + 2 * c) * RW;
-      uint32_t* dlo = dhi + RW;
+      uint32_t* dhi = strip + (y * ROWS + c) * RW;
+      uint32_t* dlo = dhi + g.SH * CRS;
       for (int x = lane; x < g.SW; x += 64) {
         const int ix = SX0 + x;
         const float v0 = (yok & (ix >= 0) & (ix < g.W)) ? (src[ix] - cc) * scale : 0.f;
@@ -181,31 +191,35 @@ struct CtSplit {
 
   // operand A: per block, hi words then lo words; halves outside the P x P patch are zero
   __device__ static void load_a(AReg (&A)[2 * NKB], const uint32_t* strip, int base, int gp,
-                                int P) {
+                                int P, int lo) {
 #pragma unroll
     for (int b = 0; b < NKB; ++b) {
       const int c0 = 8 * cb(b) + 2 * gp;
       const uint32_t keep = (c0 < P ? 0xFFFFu : 0u) | (c0 + 1 < P ? 0xFFFF0000u : 0u);
 #pragma unroll
       for (int part = 0; part < 2; ++part) {
+        const uint32_t* pl = strip + base + (part ? lo : 0);
         u4 w;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const bool rok = 4 * rb(b) + i < P;
-          w[i] = rok ? (strip[base + woff(b, part, i)] & keep) : 0u;
+          w[i] = rok ? (pl[woff(b, i)] & keep) : 0u;
         }
         A[2 * b + part] = w;
       }
     }
   }
 
-  __device__ static void load_b(uint32_t (&B)[NB], const uint32_t* strip, int base) {
+  __device__ static void load_b(u4 (&B)[NB], const uint32_t* strip, int base, int lo) {
+    const uint32_t* sh = strip + base;
+    const uint32_t* sl = strip + base + lo;
 #pragma unroll
     for (int b = 0; b < NKB; ++b)
 #pragma unroll
-      for (int part = 0; part < 2; ++part)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) B[(2 * b + part) * 4 + i] = strip[base + woff(b, part, i)];
+      for (int i = 0; i < 4; ++i) {
+        B[2 * b][i] = sh[woff(b, i)];
+        B[2 * b + 1][i] = sl[woff(b, i)];
+      }
   }
 
   __device__ static f4 mfma(const u4& a, const u4& b, const f4& c) {
@@ -217,23 +231,20 @@ struct CtSplit {
                                                      __builtin_bit_cast(bf8, b), c, 0, 0, 0);
   }
 
-  __device__ static f4 chain_and_load(const AReg (&A)[2 * NKB], const uint32_t (&cur)[NB],
-                                      uint32_t (&nxt)[NB], const uint32_t* strip, int nb) {
+  __device__ static f4 chain_and_load(const AReg (&A)[2 * NKB], const u4 (&cur)[NB],
+                                      u4 (&nxt)[NB], const uint32_t* strip, int nb, int lo) {
+    const uint32_t* sh = strip + nb;
+    const uint32_t* sl = strip + nb + lo;
     f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int b = 0; b < NKB; ++b) {
-      const u4 bhi = {cur[(2 * b) * 4 + 0], cur[(2 * b) * 4 + 1], cur[(2 * b) * 4 + 2],
-                      cur[(2 * b) * 4 + 3]};
-      const u4 blo = {cur[(2 * b + 1) * 4 + 0], cur[(2 * b + 1) * 4 + 1], cur[(2 * b + 1) * 4 + 2],
-                      cur[(2 * b + 1) * 4 + 3]};
-      acc = mfma(A[2 * b], bhi, acc);      // hi * hi
-      acc = mfma(A[2 * b], blo, acc);      // hi * lo
-      acc = mfma(A[2 * b + 1], bhi, acc);  // lo * hi
+      acc = mfma(A[2 * b], cur[2 * b], acc);          // hi * hi
+      acc = mfma(A[2 * b], cur[2 * b + 1], acc);      // hi * lo
+      acc = mfma(A[2 * b + 1], cur[2 * b], acc);      // lo * hi
 #pragma unroll
-      for (int part = 0; part < 2; ++part)
+      for (int i = 0; i < 4; ++i) nxt[2 * b][i] = sh[woff(b, i)];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          nxt[(2 * b + part) * 4 + i] = strip[nb + woff(b, part, i)];
+      for (int i = 0; i < 4; ++i) nxt[2 * b + 1][i] = sl[woff(b, i)];
     }
     return acc;
   }

@@ -87,7 +87,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
                                            const DepthWin* dw = nullptr) {
   constexpr int CRS = CT::CRS;
   constexpr int NB = CT::NB;
-  using BReg = std::conditional_t<std::is_same_v<typename CT::AReg, float>, float, uint32_t>;
+  using BReg = typename CT::BReg;
   constexpr int NA = std::is_same_v<typename CT::AReg, float> ? CT::NS : 2 * (CT::NS / 3);
   constexpr int TL = RefSelect<KR>::TL;
   static_assert(NT >= 1 && NT <= 4, "tile columns");
@@ -166,7 +166,9 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
   // ---- operand A: reference i = p16 -> block position (i/4, i%4); zero the padding
   //      elements of odd patch sides
   typename CT::AReg A[NA];
-  CT::load_a(A, strip, (s * (p16 >> 2) + r) * CRS + (s * (p16 & 3) + r) + lane_off, gp, P);
+  const int plane = CT::plane_off(g);  // split forms: hi plane -> lo plane
+  CT::load_a(A, strip, (s * (p16 >> 2) + r) * CRS + (s * (p16 & 3) + r) + lane_off, gp, P,
+             plane);
 
   // ---- selection state for references (row gp, column v); norms with the column part of
   //      the window folded in
@@ -229,14 +231,14 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
     float p_ybias = INFINITY;
     int p_nrow = 0, p_jrow = 0, p_tx = 0;
     int qy = first;
-    CT::load_b(bufA, strip, (qy - SY0) * CRS + bl);
+    CT::load_b(bufA, strip, (qy - SY0) * CRS + bl, plane);
     // tile (qy, TX) with operands in `cur`; loads the next tile into `nxt`
     auto tile = [&](auto TXc, BReg (&cur)[NB], BReg (&nxt)[NB]) __attribute__((always_inline)) {
       constexpr int TX = decltype(TXc)::value;
       __builtin_amdgcn_sched_barrier(0);
       const int nqy = (TX + 1 < NT) ? qy : min(qy + stride, qy_hi);
       const int nrb = (nqy - SY0) * CRS + bl + ((TX + 1 < NT) ? kTileN * (TX + 1) : 0);
-      const f4 acc = CT::chain_and_load(A, cur, nxt, strip, nrb);
+      const f4 acc = CT::chain_and_load(A, cur, nxt, strip, nrb, plane);
       const float ns = nstrip[p_nrow + p16 + kTileN * p_tx];
       // d = X * acc + (column part + Y): Euclidean X = mc, Y = ||X_j||^2 + row mask;
       // NCC X = -post/||X_j||, Y = row mask
