@@ -4,12 +4,14 @@
 // h_X (.) h_X (Sec. III-B, the normalisation vector h_X; used by Lemma 2).  center_c comes
 // from the centring pass when centring is on (centers[c]); otherwise it is zero.
 //
-// One workgroup produces a 16 x 64 output tile.  It stages the (16+P-1) x (64+P-1) input
-// window of one channel in LDS with coalesced row loads, forms the horizontal P-tap sums of
-// squares, then the vertical P-tap sums, and accumulates over channels.  Sums are direct
-// (no prefix or summed-area tables, whose rounding grows with the image) and carried in
-// float64, so every output is the float32 rounding of the exact norm.  HBM-bound: each
-// input element is read once from HBM and each output written once.
+// One workgroup of 256 threads produces a kNormTY x kNormTX output tile (one output per
+// thread; 8 x 32, so a 512 x 512 image gives 1024 workgroups and every compute unit has
+// several to overlap their load / sum / store phases).  It stages the (TY+P-1) x (TX+P-1)
+// input window of one channel in LDS with coalesced row loads, forms the horizontal P-tap
+// sums of squares, then the vertical P-tap sums, and accumulates over channels.  Sums are
+// direct (no prefix or summed-area tables, whose rounding grows with the image) and
+// carried in float64, so every output is the float32 rounding of the exact norm.  Each
+// input element is read once from HBM (halos come from L2) and each output written once.
 //
 // Each tile also writes max |x - center_c| over its staged window (all channels) to a
 // per-tile map when asked; the float16 split form takes its per-block pre-scale from it.
@@ -25,6 +27,8 @@ namespace bmk {
 
 constexpr int kMaxP = 16;
 
+static_assert(kNormTX * kNormTY == 256, "one output per thread");
+
 struct NormLds {
   float tile[kNormTY + kMaxP - 1][kNormTX + kMaxP];
   double hs[kNormTY + kMaxP - 1][kNormTX];
@@ -34,59 +38,52 @@ struct NormLds {
 __device__ __forceinline__ void norm_tile(const float* __restrict__ img, float* __restrict__ out,
                                           const NormGeom& g, const float* __restrict__ centers,
                                           float* __restrict__ amax, int bx, int by, NormLds& sh) {
-  const int tx = threadIdx.x & 63;
-  const int ty = threadIdx.x >> 6;  // 0..3
+  const int t = threadIdx.x;
   const int ox0 = bx * kNormTX;
   const int oy0 = by * kNormTY;
   const int rows = kNormTY + g.P - 1;
   const int cols = kNormTX + g.P - 1;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int orow = t / kNormTX, ocol = t - (t / kNormTX) * kNormTX;  // this thread's output
+  double acc = 0.0;
   float vmax = 0.f;
 
   for (int c = 0; c < g.C; ++c) {
     const float* plane = img + (size_t)c * g.H * g.W;
     const float cc = centers ? centers[c] : 0.f;
-    for (int rr = ty; rr < rows; rr += 4) {
-      const int y = oy0 + rr;
-      for (int xx = tx; xx < cols; xx += 64) {
-        const int x = ox0 + xx;
-        float v = 0.f;
-        if (y < g.H && x < g.W) v = plane[(size_t)y * g.W + x] - cc;
-        sh.tile[rr][xx] = v;
-        vmax = fmaxf(vmax, fabsf(v));
-      }
+    for (int i = t; i < rows * cols; i += 256) {
+      const int rr = i / cols, xx = i - (i / cols) * cols;
+      const int y = oy0 + rr, x = ox0 + xx;
+      float v = 0.f;
+      if (y < g.H && x < g.W) v = plane[(size_t)y * g.W + x] - cc;
+      sh.tile[rr][xx] = v;
+      vmax = fmaxf(vmax, fabsf(v));
     }
     __syncthreads();
-    for (int rr = ty; rr < rows; rr += 4) {
+    for (int i = t; i < rows * kNormTX; i += 256) {
+      const int rr = i / kNormTX, cx = i - (i / kNormTX) * kNormTX;
       double s = 0.0;
       for (int m = 0; m < g.P; ++m) {
-        const double v = (double)sh.tile[rr][tx + m];
+        const double v = (double)sh.tile[rr][cx + m];
         s += v * v;
       }
-      sh.hs[rr][tx] = s;
+      sh.hs[rr][cx] = s;
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int row = ty * 4 + k;
-      double s = 0.0;
-      for (int l = 0; l < g.P; ++l) s += sh.hs[row + l][tx];
-      acc[k] += s;
-    }
+    double s = 0.0;
+    for (int l = 0; l < g.P; ++l) s += sh.hs[orow + l][ocol];
+    acc += s;
     __syncthreads();
   }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int oy = oy0 + ty * 4 + k;
-    const int ox = ox0 + tx;
-    if (oy < g.Hv && ox < g.Wv) out[(size_t)oy * g.Wv + ox] = (float)acc[k];
+  {
+    const int oy = oy0 + orow, ox = ox0 + ocol;
+    if (oy < g.Hv && ox < g.Wv) out[(size_t)oy * g.Wv + ox] = (float)acc;
   }
   if (amax) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, o));
-    if (tx == 0) sh.red[ty] = vmax;
+    if ((t & 63) == 0) sh.red[t >> 6] = vmax;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (t == 0) {
       const int ntx = (g.Wv + kNormTX - 1) / kNormTX;
       amax[by * ntx + bx] = fmaxf(fmaxf(sh.red[0], sh.red[1]), fmaxf(sh.red[2], sh.red[3]));
     }
