@@ -53,21 +53,34 @@ struct CtF32 {
   __device__ static int lane_off(int gp) { return (gp >> 1) * CRS + (gp & 1); }
   __device__ static int plane_off(const FastGeom&) { return 0; }  // one plane
 
-  // strip rows (y*C + c): the centred image values, zero outside the image
+  // strip rows (y*C + c): the centred image values, zero outside the image.  Four rows per
+  // pass, loads unconditional (clamped to a valid address, masked afterwards) so they are
+  // in flight together.
   __device__ static void stage(uint32_t* strip, const float* img, const FastGeom& g, int SY0,
                                int SX0, int first, int step, int lane, const float* center,
                                float) {
-    for (int row = first; row < g.SH * C; row += step) {
-      const int y = row / C;
-      const int c = row - y * C;
-      const int iy = SY0 + y;
-      const bool yok = (iy >= 0) & (iy < g.H);
-      const float cc = center[c];
-      const float* src = img + ((size_t)c * g.H + (yok ? iy : 0)) * g.W;
-      float* dst = reinterpret_cast<float*>(strip) + row * RW;
+    const int n = g.SH * C;
+    for (int row0 = first; row0 < n; row0 += 4 * step) {
       for (int x = lane; x < g.SW; x += 64) {
         const int ix = SX0 + x;
-        dst[x] = (yok & (ix >= 0) & (ix < g.W)) ? src[ix] - cc : 0.f;
+        const bool xok = (ix >= 0) & (ix < g.W);
+        float v[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int row = row0 + u * step;
+          const int y = row / C;
+          const int c = row - y * C;
+          const int iy = SY0 + y;
+          ok[u] = (row < n) & (iy >= 0) & (iy < g.H) & xok;
+          v[u] = img[ok[u] ? ((size_t)c * g.H + iy) * g.W + ix : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int row = row0 + u * step;
+          if (row < n)
+            reinterpret_cast<float*>(strip)[row * RW + x] = ok[u] ? v[u] - center[row % C] : 0.f;
+        }
       }
     }
   }
@@ -163,28 +176,48 @@ struct CtSplit {
   // words from the hi plane to the lo plane
   __device__ static int plane_off(const FastGeom& g) { return g.SH * CRS; }
 
+  // Strip word x of a row = (v[x], v[x+1]) of the row's 16-bit parts (the pixel pair that
+  // starts at x), zero outside the image and past the strip width.  Lane x stages word x
+  // (the strip width is at most 64 words): it loads and splits pixel x once and takes the
+  // parts of pixel x+1 from lane x+1 (a wave-wide DPP shift; the last lane gets zeros).
+  // Four rows per pass, loads unconditional (clamped to a valid address, masked
+  // afterwards) so they are in flight together.
   __device__ static void stage(uint32_t* strip, const float* img, const FastGeom& g, int SY0,
                                int SX0, int first, int step, int lane, const float* center,
                                float scale) {
-    for (int row = first; row < g.SH * C; row += step) {
-      const int y = row / C;
-      const int c = row - y * C;
-      const int iy = SY0 + y;
-      const bool yok = (iy >= 0) & (iy < g.H);
-      const float cc = center[c];
-      const float* src = img + ((size_t)c * g.H + (yok ? iy : 0)) * g.W;
-      uint32_t* dhi = strip + (y * ROWS + c) * RW;
-      uint32_t* dlo = dhi + g.SH * CRS;
-      for (int x = lane; x < g.SW; x += 64) {
-        const int ix = SX0 + x;
-        const float v0 = (yok & (ix >= 0) & (ix < g.W)) ? (src[ix] - cc) * scale : 0.f;
-        const float v1 = (yok & (ix + 1 >= 0) & (ix + 1 < g.W) & (x + 1 < g.SW))
-                             ? (src[ix + 1] - cc) * scale : 0.f;
-        uint32_t h0, l0, h1, l1;
-        split2<FP16>(v0, h0, l0);
-        split2<FP16>(v1, h1, l1);
-        dhi[x] = h0 | (h1 << 16);
-        dlo[x] = l0 | (l1 << 16);
+    const int n = g.SH * C;
+    const int lo_plane = g.SH * CRS;
+    const int x = lane;
+    const int ix = SX0 + x;
+    const bool xok = (x < g.SW) & (ix >= 0) & (ix < g.W);
+    for (int row0 = first; row0 < n; row0 += 4 * step) {
+      float v[4];
+      bool ok[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = row0 + u * step;
+        const int y = row / C;
+        const int c = row - y * C;
+        const int iy = SY0 + y;
+        ok[u] = (row < n) & (iy >= 0) & (iy < g.H) & xok;
+        v[u] = img[ok[u] ? ((size_t)c * g.H + iy) * g.W + ix : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int row = row0 + u * step;
+        const float val = ok[u] ? (v[u] - center[row % C]) * scale : 0.f;
+        uint32_t h0, l0;
+        split2<FP16>(val, h0, l0);
+        // DPP wave_shl:1 -- lane i reads lane i + 1; lane 63 keeps the zero
+        const uint32_t h1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)h0, 0x130, 0xF, 0xF, false);
+        const uint32_t l1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)l0, 0x130, 0xF, 0xF, false);
+        if ((row < n) & (x < g.SW)) {
+          const int y = row / C;
+          const int c = row - y * C;
+          uint32_t* dhi = strip + (y * ROWS + c) * RW;
+          dhi[x] = h0 | (h1 << 16);
+          dhi[lo_plane + x] = l0 | (l1 << 16);
+        }
       }
     }
   }

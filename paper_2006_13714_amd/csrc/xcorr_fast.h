@@ -140,16 +140,26 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
   auto stage_slab = [&](const float* __restrict__ im, const float* __restrict__ nm)
                         __attribute__((always_inline)) {
     CT::stage(strip, im, g, SY0, SX0, wave, S, lane, center, scale);
-    for (int y = wave; y < g.NH; y += S) {
-      const int qy = SY0 + y;
-      const bool yok = (qy >= 0) & (qy < g.Hv);
-      const float* src = nm + (size_t)(yok ? qy : 0) * g.Wv;
-      float* dst = nstrip + y * NW;
+    // norm strip: four rows per pass, loads unconditional (clamped) and masked afterwards
+    for (int y0 = wave; y0 < g.NH; y0 += 4 * S) {
       for (int x = lane; x < NW; x += 64) {
         const int qx = SX0 + x;
-        const bool ok = yok & (qx >= 0) & (qx < g.Wv);
-        const float n = ok ? src[qx] : 0.f;
-        dst[x] = ncc ? (n > 0.f ? -post / sqrtf(n) : 0.f) : (ok ? n : INFINITY);
+        const bool xok = (qx >= 0) & (qx < g.Wv);
+        float nv[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int qy = SY0 + y0 + u * S;
+          ok[u] = (y0 + u * S < g.NH) & (qy >= 0) & (qy < g.Hv) & xok;
+          nv[u] = nm[ok[u] ? (size_t)qy * g.Wv + qx : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (y0 + u * S >= g.NH) continue;
+          const float n = ok[u] ? nv[u] : 0.f;
+          nstrip[(y0 + u * S) * NW + x] =
+              ncc ? (n > 0.f ? -post / sqrtf(n) : 0.f) : (ok[u] ? n : INFINITY);
+        }
       }
     }
   };
