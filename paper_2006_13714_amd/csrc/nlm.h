@@ -66,14 +66,22 @@ nlm_fast(const float* __restrict__ img, const float* __restrict__ nrm,
 #pragma unroll
   for (int c = 0; c < 8; ++c) center[c] = 0.f;
   CT::stage(reinterpret_cast<uint32_t*>(strip), img, g, SY0, SX0, wave, S, lane, center, 1.f);
-  for (int y = wave; y < g.NH; y += S) {
-    const int qy = SY0 + y;
-    const bool yok = (qy >= 0) & (qy < g.Hv);
-    const float* src = nrm + (size_t)(yok ? qy : 0) * g.Wv;
-    float* dst = nstrip + y * NW;
+  // norm strip: four rows per pass, loads unconditional (clamped) and masked afterwards
+  for (int y0 = wave; y0 < g.NH; y0 += 4 * S) {
     for (int x = lane; x < NW; x += 64) {
       const int qx = SX0 + x;
-      dst[x] = (yok & (qx >= 0) & (qx < g.Wv)) ? src[qx] : INFINITY;
+      const bool xok = (qx >= 0) & (qx < g.Wv);
+      float nv[4];
+      bool ok[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int qy = SY0 + y0 + u * S;
+        ok[u] = (y0 + u * S < g.NH) & (qy >= 0) & (qy < g.Hv) & xok;
+        nv[u] = nrm[ok[u] ? (size_t)qy * g.Wv + qx : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (y0 + u * S < g.NH) nstrip[(y0 + u * S) * NW + x] = ok[u] ? nv[u] : INFINITY;
     }
   }
   __syncthreads();

@@ -46,15 +46,24 @@
 namespace bmk {
 
 // Upper bound of max |x - centre| over the strip rows [y0, y1] x columns [x0, x1] (image
-// coordinates, already clipped): the largest entry of the norm pass's per-tile map over
-// the tiles that hold those pixels.  Wave-uniform.
+// coordinates, already clipped) in `nmap` stacked per-tile maps of the norm pass (`stride`
+// entries apart): the largest entry over the tiles that hold those pixels.  The lanes read
+// the entries in parallel and a wave-wide max reduces them; the result is the same in
+// every lane and every wave.
 __device__ __forceinline__ float strip_absmax(const float* __restrict__ amax, const FastGeom& g,
-                                              int y0, int y1, int x0, int x1) {
+                                              int y0, int y1, int x0, int x1, int lane,
+                                              int nmap = 1, size_t stride = 0) {
   const int ty0 = min(y0 / kNormTY, g.nty - 1), ty1 = min(y1 / kNormTY, g.nty - 1);
   const int tx0 = min(x0 / kNormTX, g.ntx - 1), tx1 = min(x1 / kNormTX, g.ntx - 1);
+  const int nx = tx1 - tx0 + 1, per = nx * (ty1 - ty0 + 1);
   float m = 0.f;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx) m = fmaxf(m, amax[ty * g.ntx + tx]);
+  for (int i = lane; i < per * nmap; i += 64) {
+    const int k = i / per, e = i - k * per;
+    const int ty = ty0 + e / nx, tx = tx0 + e - (e / nx) * nx;
+    m = fmaxf(m, amax[k * stride + (size_t)ty * g.ntx + tx]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
   return m;
 }
 
@@ -119,13 +128,11 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
     const int y0 = max(SY0, 0), y1 = min(SY0 + g.SH, g.H) - 1;
     const int x0 = max(SX0, 0), x1 = min(SX0 + g.SW, g.W) - 1;
     float m;
-    if constexpr (D3) {  // one scale for every slab the block stages (the reference's included)
-      m = 0.f;
-      for (int zc = dw->z0; zc <= dw->z1; ++zc)
-        m = fmaxf(m, strip_absmax(dw->amax + (size_t)zc * dw->tiles, g, y0, y1, x0, x1));
-    } else {
-      m = strip_absmax(amax, g, y0, y1, x0, x1);
-    }
+    if constexpr (D3)  // one scale for every slab the block stages (the reference's included)
+      m = strip_absmax(dw->amax + (size_t)dw->z0 * dw->tiles, g, y0, y1, x0, x1, threadIdx.x & 63,
+                       dw->z1 - dw->z0 + 1, dw->tiles);
+    else
+      m = strip_absmax(amax, g, y0, y1, x0, x1, threadIdx.x & 63);
     const int e = m > 0.f ? ilogbf(m) + 1 : 0;  // m < 2^e
     const int k = max(-60, min(60, 14 - e));
     scale = ldexpf(1.f, k);
