@@ -186,3 +186,20 @@ def test_unsupported_uses_of_3d_plans(gpu):
         with pytest.raises(bm.BMError) as ei:
             bm.bm_plan(bm.make_desc(64, 64, 6, P, 1, Wn, 16, "fp32", 0, 2, 3))
         assert ei.value.status == bm.BM_ENOTSUP
+
+
+def test_split_scale_covers_every_slab(gpu):
+    """float16 form: the pre-scale must come from the largest magnitude over all slabs a
+    block stages.  Frames alternate between values near 1 and near 60, so a scale taken from
+    a small frame alone would overflow float16 (60 * 2^13 > 65504) in the large neighbours;
+    float16 keeps relative precision, so the correct scale meets the float32 tolerance."""
+    banner("3d fp16x3 scale over slabs")
+    rng = np.random.default_rng(12)
+    q, H, W = 5, 36, 40
+    base = rng.uniform(0.0, 1.0, size=(q, H, W))
+    gain = np.array([1.0, 60.0, 1.0, 60.0, 1.0])[:, None, None]
+    v = (base * gain).astype(np.float32)
+    P, d, s, Wn, c, K = 6, 1, 2, 13, 3, 12
+    idx, dist = run3d(v, P, d, s, Wn, c, K, "fp16x3")
+    assert np.all(np.isfinite(dist[idx >= 0]))
+    print(assert_parity(v, P, d, s, Wn, c, K, idx, dist, "fp16x3"))
