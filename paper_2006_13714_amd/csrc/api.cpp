@@ -73,7 +73,8 @@ bm_status validate_desc(const bm_desc* d) {
 // reference block per wave, channel-plane strip.  Specialised kernel (`fast`): one
 // reference block per workgroup shared by wy waves (wx unused), channel-interleaved strip
 // rows of kFastRS floats.  `cap`: candidate buffer entries per reference.
-void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) {
+void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g,
+               bool fast_norm_strip) {
   memset(&g, 0, sizeof(g));
   g.H = d.height;
   g.W = d.width;
@@ -114,7 +115,7 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) 
   g.SW = g.NW + pcol - 1;
   g.prec = d.precision;
   g.metric = (d.flags & BM_FLAG_NCC) ? 1 : 0;
-  g.RS = fast ? (d.precision == BM_PREC_FP32 ? kFastRS : kSplitRW) : g.SW;
+  g.RS = fast ? (d.precision == BM_PREC_FP32 ? kFastRS : split_rw(d.channels)) : g.SW;
   g.PLANE = g.SH * g.RS;
   g.CAP = cap;
   const int h2 = g.Pe / 2;
@@ -136,7 +137,9 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g) 
   const int nw = wy * wx;
   const int rows_per_img_row = (fast && d.precision != BM_PREC_FP32) ? 2 * g.C : g.C;
   const int strip_bytes = rows_per_img_row * g.SH * g.RS * 4;
-  const int norm_bytes = g.NH * g.NRS * 4;
+  // the specialised BM kernels read candidate norms from the norm map (L2); the generic
+  // kernel and non-local means stage them in LDS
+  const int norm_bytes = (fast && !fast_norm_strip) ? 0 : g.NH * g.NRS * 4;
   int buf_bytes = nw * 16 * cap * 8;
   if (fast) {
     const int kr = d.k <= 16 ? 1 : 2;
@@ -234,9 +237,18 @@ bm_status bm_plan(const bm_desc* desc, bm_plan_t* out) {
       st = fail(BM_ENOTSUP, "3D search needs patch 3..8 (5..8 split), K <= 32 and "
                             "3*stride + window <= 48");
     } else {
-      e = prepare_xcorr_depth(p->desc.precision, p->desc.channels, (p->desc.patch + 1) / 2,
-                              p->kr, p->geom.NT, p->geom.lds_bytes);
-      if (e != hipSuccess) st = hip_fail(e, "hipFuncSetAttribute");
+      // the 3D kernel stages candidate norms in LDS with each slab's strip
+      XcGeom g3;
+      fill_geom(p->desc, p->cfg.wy, 1, p->cfg.cap, true, g3, true);
+      g3.p1_step = p->cfg.p1;
+      if (g3.lds_bytes > max_lds) {
+        st = fail(BM_ENOTSUP, "3D tile needs %d bytes of LDS (limit %d)", g3.lds_bytes, max_lds);
+      } else {
+        p->geom = g3;
+        e = prepare_xcorr_depth(p->desc.precision, p->desc.channels, (p->desc.patch + 1) / 2,
+                                p->kr, p->geom.NT, p->geom.lds_bytes);
+        if (e != hipSuccess) st = hip_fail(e, "hipFuncSetAttribute");
+      }
     }
     if (st == BM_OK && (int64_t)p->geom.nwg_total * p->Z >= ((int64_t)1 << 31))
       st = fail(BM_EINVAL, "3D problem too large for one launch");
@@ -348,7 +360,7 @@ bm_status bm_nlm(bm_plan_t plan, const float* d_img, float b, float* d_patch, fl
   bm_status st = run_norms(*plan, d_img, nrm, plan_aux(*plan, ws), s);
   if (st != BM_OK) return st;
   XcGeom g;
-  fill_geom(d, plan->cfg.wy < 4 ? plan->cfg.wy : 4, 1, plan->cfg.cap, true, g);
+  fill_geom(d, plan->cfg.wy < 4 ? plan->cfg.wy : 4, 1, plan->cfg.cap, true, g, true);
   hipError_t e = launch_nlm(d_img, nrm, d_patch, d_theta, g, b, s);
   if (e != hipSuccess) return hip_fail(e, "NLM launch");
   return BM_OK;

@@ -14,6 +14,10 @@ constexpr int kRefBlock = 4;      // a wave owns a 4 x 4 block of references
 constexpr int kTileN = 16;        // candidates per matrix tile (one row segment)
 constexpr int kFastRS = 80;       // LDS row stride (words) of the specialised float32 kernel
 constexpr int kSplitRW = 64;      // LDS row stride (words) of the specialised split kernels
+// Split-form row stride by channel count: the widest strip row is 3 * 16 + 8 - 1 = 55 words;
+// one channel uses exactly that (so a 4-wave block fits four workgroups per compute unit),
+// more channels keep 64 so that an operand's rows stay within the reads' offset range.
+constexpr int split_rw(int C) { return C == 1 ? 55 : kSplitRW; }
 
 // Output tile of the norm pass.  Tile (tx, ty) stages the input window rows
 // [8 ty, 8 ty + 8 + P - 1) x columns [32 tx, 32 tx + 32 + P - 1), clipped to the image,

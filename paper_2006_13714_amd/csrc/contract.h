@@ -148,7 +148,7 @@ __device__ __forceinline__ void split2(float v, uint32_t& hi, uint32_t& lo) {
 
 template <int C, int H2, bool FP16>
 struct CtSplit {
-  static constexpr int RW = kSplitRW;
+  static constexpr int RW = split_rw(C);
   static constexpr int ROWS = C;              // per image row and plane: channel c -> row c
   static constexpr int CRS = ROWS * RW;
   static constexpr int PE = 2 * H2;

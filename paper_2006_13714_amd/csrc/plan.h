@@ -45,7 +45,9 @@ bm_status fail(bm_status s, const char* fmt, ...);
 bm_status hip_fail(hipError_t e, const char* what);
 const char* last_error();
 bm_status validate_desc(const bm_desc* d);
-void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g);
+// fast_norm_strip: the specialised layout with an LDS norm strip (non-local means)
+void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g,
+               bool fast_norm_strip = false);
 
 bool fast_eligible(const bm_desc& d);
 // The 2D problem of one slab of a 3D descriptor (channels = patch_depth); 2D: d itself.

@@ -85,7 +85,10 @@ struct DepthWin {
 // Every thread of the workgroup must call it (it synchronises).  With D3 the candidates
 // are those of the slabs in `dw` (visited in increasing depth, restaged per slab, one
 // selection state across all of them) and indices are volume positions (z' H + qy) W + qx.
-template <class CT, int C, int KR, int NT, bool D3 = false>
+// NSTRIP: candidate norms staged in LDS with the pixel strip (the layout's norm strip)
+// instead of read from the norm map a row ahead; the single-image kernels read the map,
+// whose smaller LDS footprint is what lets them keep more workgroups per compute unit.
+template <class CT, int C, int KR, int NT, bool D3 = false, bool NSTRIP = true>
 __device__ __forceinline__ void fast_block(const float* __restrict__ img,
                                            const float* __restrict__ nrm,
                                            const float* __restrict__ centers,
@@ -102,7 +105,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
   static_assert(NT >= 1 && NT <= 4, "tile columns");
   constexpr int NW = kTileN * NT;  // norm strip row length
   uint32_t* strip = reinterpret_cast<uint32_t*>(lds + g.lds_strip_off);
-  float* nstrip = reinterpret_cast<float*>(lds + g.lds_norm_off);
+  float* nstrip = reinterpret_cast<float*>(lds + g.lds_norm_off);  // NSTRIP only
   Entry* buf_all = reinterpret_cast<Entry*>(lds + g.lds_buf_off);
 
   const int tid = threadIdx.x;
@@ -141,31 +144,37 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
   const bool ncc = g.metric != 0;  // wave-uniform
   const float post = -0.5f * mc;   // removes the split forms' pre-scale (power of two)
 
-  // ---- stage the strip (policy layout; zero outside the image) and the norm strip:
-  //      Euclidean ||X_j||^2 (+inf outside the valid positions), NCC -post/||X_j|| (0 for a
-  //      zero patch and outside the valid positions, which the column masks exclude)
+  // Candidate norms as the epilogue uses them: Euclidean ||X_j||^2 (+inf outside the valid
+  // positions), NCC -post/||X_j|| (0 for a zero patch and outside the valid positions,
+  // which the column masks exclude).  Without NSTRIP they are read from the norm map (L2
+  // resident) a row ahead of use.
+  const float npost = -post;
+  auto cand_norm = [&](float n, bool ok) __attribute__((always_inline)) {
+    return ncc ? ((ok & (n > 0.f)) ? npost / sqrtf(n) : 0.f) : (ok ? n : INFINITY);
+  };
+  const float* nm_cur = nrm;  // norm map of the candidates' slab
+
+  // ---- stage the strip (policy layout; zero outside the image) and, with NSTRIP, the norm
+  //      strip (four rows per pass, loads unconditional (clamped) and masked afterwards)
   auto stage_slab = [&](const float* __restrict__ im, const float* __restrict__ nm)
                         __attribute__((always_inline)) {
     CT::stage(strip, im, g, SY0, SX0, wave, S, lane, center, scale);
-    // norm strip: four rows per pass, loads unconditional (clamped) and masked afterwards
-    for (int y0 = wave; y0 < g.NH; y0 += 4 * S) {
-      for (int x = lane; x < NW; x += 64) {
-        const int qx = SX0 + x;
-        const bool xok = (qx >= 0) & (qx < g.Wv);
-        float nv[4];
-        bool ok[4];
+    if constexpr (NSTRIP) {
+      for (int y0 = wave; y0 < g.NH; y0 += 4 * S) {
+        for (int x = lane; x < NW; x += 64) {
+          const int qx = SX0 + x;
+          const bool xok = (qx >= 0) & (qx < g.Wv);
+          float nv[4];
+          bool ok[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int qy = SY0 + y0 + u * S;
-          ok[u] = (y0 + u * S < g.NH) & (qy >= 0) & (qy < g.Hv) & xok;
-          nv[u] = nm[ok[u] ? (size_t)qy * g.Wv + qx : 0];
-        }
+          for (int u = 0; u < 4; ++u) {
+            const int qy = SY0 + y0 + u * S;
+            ok[u] = (y0 + u * S < g.NH) & (qy >= 0) & (qy < g.Hv) & xok;
+            nv[u] = nm[ok[u] ? (size_t)qy * g.Wv + qx : 0];
+          }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (y0 + u * S >= g.NH) continue;
-          const float n = ok[u] ? nv[u] : 0.f;
-          nstrip[(y0 + u * S) * NW + x] =
-              ncc ? (n > 0.f ? -post / sqrtf(n) : 0.f) : (ok[u] ? n : INFINITY);
+          for (int u = 0; u < 4; ++u)
+            if (y0 + u * S < g.NH) nstrip[(y0 + u * S) * NW + x] = cand_norm(nv[u], ok[u]);
         }
       }
     }
@@ -196,11 +205,13 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
     float norms[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      norms[v] = nstrip[(s * gp + r) * NW + s * v + r];
+      // reference (ryw + s gp, rxw + s v); padding references read a clamped position
+      const int ry = min(ryw + s * gp, g.Hv - 1), rx = min(rxw + s * v, g.Wv - 1);
+      norms[v] = cand_norm(nrm[(size_t)ry * g.Wv + rx], true);
       valid[v] = (gp <= a_max) & (v <= b_max);
     }
     sel.init(buf_all + (size_t)wave * 16 * g.CAP, g.CAP, g.K, lane, norms, valid);
-    // NCC outputs 2 - 2 NCC = 2 + (2/||X_i||) e''; the strip holds -post/||X_i|| here
+    // NCC outputs 2 - 2 NCC = 2 + (2/||X_i||) e''; norms[v] holds -post/||X_i|| here
     sel.ncc = ncc;
 #pragma unroll
     for (int v = 0; v < 4; ++v) sel.outk[v] = -2.f * norms[v] / post;
@@ -219,6 +230,9 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
   const int qy_hi = min(g.Hv - 1, ryw + s * a_max + r);
   const int xs = rxw - r;  // first candidate column of the block
   const int bl = lane_off + p16;  // operand B lane offset within a strip row
+  bool colok_t[NT];               // this lane's candidate column of tile t is a valid position
+#pragma unroll
+  for (int t = 0; t < NT; ++t) colok_t[t] = (unsigned)(xs + kTileN * t + p16) < (unsigned)g.Wv;
 
   // Candidate index of (slab, row 0, column 0): 0 in 2D; set per slab by over_slabs.
   int jofs = 0;
@@ -228,9 +242,10 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
       body();
     } else {
       for (int zc = dw->z0; zc <= dw->z1; ++zc) {
-        __syncthreads();  // every wave is done with the strips
+        __syncthreads();  // every wave is done with the strip
         stage_slab(dw->vol + (size_t)zc * g.H * g.W, dw->nrm + (size_t)zc * g.Hv * g.Wv);
         __syncthreads();
+        nm_cur = dw->nrm + (size_t)zc * g.Hv * g.Wv;
         jofs = zc * g.H * g.W;
         body();
       }
@@ -245,10 +260,23 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
     BReg bufA[NB], bufB[NB];
     f4 accp = {0.f, 0.f, 0.f, 0.f};
     // carried description of the previous tile (a virtual +inf row before the first)
-    float p_ybias = INFINITY;
+    float p_ybias = INFINITY, p_ns = 0.f;
     int p_nrow = 0, p_jrow = 0, p_tx = 0;
     int qy = first;
     CT::load_b(bufA, strip, (qy - SY0) * CRS + bl, plane);
+    // raw candidate norms of the current row's tiles and of the next row (loads clamped to a
+    // valid position; the column masks are applied when a tile takes its value)
+    float ncur[NT], nnxt[NT];
+    auto load_norms = [&](float (&dst)[NT], int row) __attribute__((always_inline)) {
+      if constexpr (!NSTRIP) {
+        const float* src = nm_cur + (size_t)row * g.Wv;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) dst[t] = src[colok_t[t] ? xs + kTileN * t + p16 : 0];
+      } else {
+        (void)dst, (void)row;
+      }
+    };
+    load_norms(ncur, qy);
     // tile (qy, TX) with operands in `cur`; loads the next tile into `nxt`
     auto tile = [&](auto TXc, BReg (&cur)[NB], BReg (&nxt)[NB]) __attribute__((always_inline)) {
       constexpr int TX = decltype(TXc)::value;
@@ -256,7 +284,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
       const int nqy = (TX + 1 < NT) ? qy : min(qy + stride, qy_hi);
       const int nrb = (nqy - SY0) * CRS + bl + ((TX + 1 < NT) ? kTileN * (TX + 1) : 0);
       const f4 acc = CT::chain_and_load(A, cur, nxt, strip, nrb, plane);
-      const float ns = nstrip[p_nrow + p16 + kTileN * p_tx];
+      const float ns = NSTRIP ? nstrip[p_nrow + p16 + kTileN * p_tx] : p_ns;
       // d = X * acc + (column part + Y): Euclidean X = mc, Y = ||X_j||^2 + row mask;
       // NCC X = -post/||X_j||, Y = row mask
       const float X = ncc ? ns : mc;
@@ -267,9 +295,10 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
       post(res, p_jrow + kTileN * p_tx + p16);
       accp = acc;
       p_tx = TX;
+      if constexpr (!NSTRIP) p_ns = cand_norm(ncur[TX], colok_t[TX]);
       if constexpr (TX == 0) {
         p_ybias = ((unsigned)(qy - ryw - s * gp + r) <= (unsigned)r2) ? 0.f : INFINITY;
-        p_nrow = (qy - SY0) * NW;
+        if constexpr (NSTRIP) p_nrow = (qy - SY0) * NW;
         p_jrow = jofs + qy * W + xs;
       }
     };
@@ -281,11 +310,15 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
       else tile(TXc, bufB, bufA);
     };
     auto row = [&](auto PARc) __attribute__((always_inline)) {
+      load_norms(nnxt, min(qy + stride, qy_hi));  // the next row's norms, a row ahead (map)
       tile_par(std::integral_constant<int, 0>{}, PARc);
       if constexpr (NT > 1) tile_par(std::integral_constant<int, 1>{}, PARc);
       if constexpr (NT > 2) tile_par(std::integral_constant<int, 2>{}, PARc);
       if constexpr (NT > 3) tile_par(std::integral_constant<int, 3>{}, PARc);
       qy += stride;
+      if constexpr (!NSTRIP)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) ncur[t] = nnxt[t];
     };
     int i = 0;
     if constexpr (NT % 2 == 0) {
@@ -298,7 +331,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
       if (i < nrows) row(std::integral_constant<int, 0>{});
     }
     // drain: epilogue of the last tile
-    const float ns = nstrip[p_nrow + p16 + kTileN * p_tx];
+    const float ns = NSTRIP ? nstrip[p_nrow + p16 + kTileN * p_tx] : p_ns;
     const float X = ncc ? ns : mc;
     const float Y = ncc ? p_ybias : ns + p_ybias;
     post(arith(accp, X, Y, p_tx), p_jrow + kTileN * p_tx + p16);
@@ -410,15 +443,22 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
   }
 }
 
+// Waves per SIMD the compiler keeps registers for: the 1-channel split blocks fit four
+// 4-wave workgroups per compute unit in LDS, so with K <= 16 (one list register) their
+// registers are held to 128 (a few spilled words); with K <= 32 that spills too much.
+template <class CT, int C, int KR>
+constexpr int fast_waves_per_eu() { return (CT::kSplit && C == 1 && KR == 1) ? 4 : 1; }
+
 // Single image: one workgroup per reference block, XCD-aware block order.
 template <class CT, int C, int KR, int NT>
 __global__ void __launch_bounds__(64 * fast_max_waves(CT::kSplit ? 1 : 0, C))
+__attribute__((amdgpu_waves_per_eu(fast_waves_per_eu<CT, C, KR>())))
 xcorr_topk_fast(const float* __restrict__ img, const float* __restrict__ nrm,
                 const float* __restrict__ centers, const float* __restrict__ amax,
                 int* __restrict__ out_idx, float* __restrict__ out_dist, const FastGeom g) {
   extern __shared__ __align__(16) unsigned char lds[];
-  fast_block<CT, C, KR, NT>(img, nrm, centers, amax, out_idx, out_dist, g,
-                            xcd_remap(blockIdx.x, g.nwg_total), lds);
+  fast_block<CT, C, KR, NT, false, false>(img, nrm, centers, amax, out_idx, out_dist, g,
+                                          xcd_remap(blockIdx.x, g.nwg_total), lds);
 }
 
 typedef void (*XcFastKernel)(const float*, const float*, const float*, const float*, int*,
@@ -440,7 +480,7 @@ xcorr_topk_depth(const float* __restrict__ vol, const float* __restrict__ nrm,
   const size_t outs = (size_t)g.nry * g.nrx * g.K;
   const int lo = z - dg.before;
   const DepthWin dw{vol, nrm, amax, max(0, lo), min(dg.Z - 1, lo + dg.c - 1), dg.tiles};
-  fast_block<CT, C, KR, NT, true>(vol + z * slab, nrm + z * nslab, nullptr,
+  fast_block<CT, C, KR, NT, true, true>(vol + z * slab, nrm + z * nslab, nullptr,
                                   amax ? amax + (size_t)z * dg.tiles : nullptr,
                                   out_idx + z * outs, out_dist + z * outs, g, blk, lds, &dw);
 }
