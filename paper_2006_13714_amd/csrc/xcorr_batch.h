@@ -38,14 +38,18 @@ __device__ __forceinline__ void batch_tier_block(const BatchXc& r, int blk, unsi
 }
 
 // waves per SIMD the compiler must leave room for: float32 tier 0 mixes 1- and 3-channel
-// bodies and keeps two; the 8-wave tier needs two per SIMD by construction
-constexpr int batch_min_waves(int prec, int tier) {
-  return tier == 1 ? 1 : ((prec == 0 || tier == 2) ? 2 : 1);
+// bodies and keeps two; the 8-wave tier needs two per SIMD by construction; the split
+// forms' 1-channel tier with K <= 16 fits three (168 registers, no spills), with larger K
+// it keeps the compiler's choice
+constexpr int batch_min_waves(int prec, int tier, int kr) {
+  if (tier == 1) return 1;
+  if (prec == 0 || tier == 2) return 2;
+  return kr == 1 ? 3 : 1;
 }
 
 template <int PREC, int KR, int NT, int TIER>
 __global__ void __launch_bounds__(64 * batch_max_waves(TIER))
-__attribute__((amdgpu_waves_per_eu(batch_min_waves(PREC, TIER))))
+__attribute__((amdgpu_waves_per_eu(batch_min_waves(PREC, TIER, KR))))
 xcorr_topk_batch(const BatchXc* __restrict__ recs, int n_recs, int n_items,
                  unsigned* __restrict__ counter) {
   extern __shared__ __align__(16) unsigned char lds[];
