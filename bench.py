@@ -100,6 +100,23 @@ def cpu_baseline(img, sh, budget_s: float):
             "host_threads_available": len(os.sched_getaffinity(0))}
 
 
+# Untimed warm-up floor per measured form: the device's clocks rise over the first tens of
+# milliseconds under load, so a few warm-up steps alone leave the first timed steps slower.
+WARM_S = 0.1
+
+
+def warm(torch, step, warmup):
+    """`warmup` untimed steps, then more (synchronised every 8) until WARM_S has passed."""
+    t0 = time.perf_counter()
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    while time.perf_counter() - t0 < WARM_S:
+        for _ in range(8):
+            step()
+        torch.cuda.synchronize()
+
+
 def run_form(bm, torch, img_t, sh, prec, steps, warmup, flags=0):
     desc = bm.make_desc(sh.height, sh.width, sh.channels, sh.patch, sh.stride, sh.window,
                         sh.k, prec, flags)
@@ -115,9 +132,7 @@ def run_form(bm, torch, img_t, sh, prec, steps, warmup, flags=0):
         bm.bm_norms(plan, img_t, nrm, stream)
         bm.bm_cross_topk(plan, img_t, nrm, idx, dist, stream)
 
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
+    warm(torch, step, warmup)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -148,9 +163,7 @@ def run_nlm(bm, torch, img_t, sh, steps, warmup):
                         device=dev)
     theta = torch.empty((plan.n_ref,), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        bm.bm_nlm(plan, img_t, NLM_B, patch, theta, None, stream)
-    torch.cuda.synchronize()
+    warm(torch, lambda: bm.bm_nlm(plan, img_t, NLM_B, patch, theta, None, stream), warmup)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
     t0 = time.perf_counter()
@@ -173,9 +186,12 @@ def run_groups(bm, torch, img_t, sh, idx, steps):
     out = torch.empty_like(img_t)
     ws = torch.empty((bm.bm_aggregate_workspace(plan),), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
-    bm.bm_gather(plan, img_t, idx, groups, stream)
-    bm.bm_aggregate(plan, groups, idx, out, ws, stream)
-    torch.cuda.synchronize()
+
+    def step():
+        bm.bm_gather(plan, img_t, idx, groups, stream)
+        bm.bm_aggregate(plan, groups, idx, out, ws, stream)
+
+    warm(torch, step, 1)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     for a, b, c in ev:
         a.record(stream)
@@ -206,10 +222,12 @@ def run_volume(bm, torch, w, prec, steps, warmup):
     idx = torch.empty((plan.n_ref, sh.k), dtype=torch.int32, device=dev)
     dist = torch.empty((plan.n_ref, sh.k), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
-    for _ in range(warmup):
+
+    def step():
         bm.bm_norms(plan, vol, nrm, stream)
         bm.bm_cross_topk(plan, vol, nrm, idx, dist, stream)
-    torch.cuda.synchronize()
+
+    warm(torch, step, warmup)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     t0 = time.perf_counter()
     for a, b, c in ev:
@@ -259,6 +277,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warm-ms", type=float, default=100.0,
+                    help="untimed warm-up floor per measured form (clock ramp-up)")
     ap.add_argument("--precision", default="fp16x3", choices=list(PEAK_TFLOPS))
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of oracle work for the CPU baseline (0 disables it)")
@@ -272,10 +292,12 @@ def main():
     ap.add_argument("--clients", type=int, default=4,
                     help="serving: client threads sharing the request stream")
     args = ap.parse_args()
+    global WARM_S
+    WARM_S = max(0.0, args.warm_ms) / 1e3
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
-              "(see the sharding notes in DESIGN.md)", file=sys.stderr)
+              "(the repository's design notes describe how the path would shard)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -328,6 +350,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "warm_floor_ms": args.warm_ms,
         "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -402,9 +425,7 @@ def bench_batch(args, bm, synth, torch):
 
         res = {}
         for name, fn in (("batch", one_batch), ("per_image", per_image)):
-            for _ in range(2):
-                fn()
-            torch.cuda.synchronize()
+            warm(torch, fn, 2)
             ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                   for _ in range(steps)]
             t0 = time.perf_counter()
