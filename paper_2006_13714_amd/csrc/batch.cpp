@@ -228,7 +228,7 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
       bool fits = true;
       for (int b : g.members) {
         XcGeom t;
-        fill_geom(e[b].plan->desc, g.ws, 1, g.cap, true, t, true);
+        fill_geom(e[b].plan->desc, g.ws, 1, g.cap, true, t, batch_norm_strip(g.prec, g.tier));
         fits &= t.lds_bytes <= max_lds;
       }
       if (fits) break;
@@ -237,7 +237,7 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
     for (int b : g.members) {
       const bm_plan_s& p = *e[b].plan;
       XcGeom xg;
-      fill_geom(p.desc, g.ws, 1, g.cap, true, xg, true);  // the batch kernel stages norms
+      fill_geom(p.desc, g.ws, 1, g.cap, true, xg, batch_norm_strip(g.prec, g.tier));
       xg.p1_step = p.cfg.p1;
       if (xg.lds_bytes > max_lds) {
         release_staging(stg, s, false);

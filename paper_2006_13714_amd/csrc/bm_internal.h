@@ -96,6 +96,11 @@ constexpr int batch_tier(int prec, int C) {
   return prec == 0 ? (C == 4 ? 1 : 0) : (C == 1 ? 0 : 2);
 }
 constexpr int batch_max_waves(int tier) { return tier == 2 ? 8 : 4; }
+// Whether a batch tier stages the candidate norms in LDS (else it reads them from each
+// image's norm map a row ahead, as the single-image kernels do): the split forms' tiers
+// read the map (less LDS per block, more blocks per compute unit), the float32 tiers,
+// which gain nothing from it, keep the strip.
+constexpr bool batch_norm_strip(int prec, int tier) { return (void)tier, prec == 0; }
 
 struct NormGeom {
   int H, W, C, P, Hv, Wv;

@@ -45,7 +45,8 @@ bm_status fail(bm_status s, const char* fmt, ...);
 bm_status hip_fail(hipError_t e, const char* what);
 const char* last_error();
 bm_status validate_desc(const bm_desc* d);
-// fast_norm_strip: the specialised layout with an LDS norm strip (non-local means)
+// fast_norm_strip: the specialised layout with an LDS norm strip (non-local means, the 3D
+// kernels and the float32 batch tiers)
 void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g,
                bool fast_norm_strip = false);
 

@@ -20,21 +20,23 @@
 
 namespace bmk {
 
-template <int PREC, int KR, int NT, int C, int H2>
+template <int PREC, int KR, int NT, int C, int H2, bool NSTRIP>
 __device__ __forceinline__ void batch_block(const BatchXc& r, int blk, unsigned char* lds) {
   if constexpr (PREC != 0 && H2 < 3) {
     // split forms need patch sides 5..8; the host never forms such items
     (void)r, (void)blk, (void)lds;
   } else {
-    fast_block<CtFor<PREC, C, H2>, C, KR, NT>(r.img, r.nrm, r.centers, r.amax, r.idx, r.dist,
-                                              r.g, blk, lds);
+    fast_block<CtFor<PREC, C, H2>, C, KR, NT, false, NSTRIP>(r.img, r.nrm, r.centers, r.amax,
+                                                             r.idx, r.dist, r.g, blk, lds);
   }
 }
 
 template <int PREC, int KR, int NT, int TIER, int C, int H2>
 __device__ __forceinline__ void batch_tier_block(const BatchXc& r, int blk, unsigned char* lds) {
-  if constexpr (batch_tier(PREC, C) == TIER) batch_block<PREC, KR, NT, C, H2>(r, blk, lds);
-  else (void)r, (void)blk, (void)lds;
+  if constexpr (batch_tier(PREC, C) == TIER)
+    batch_block<PREC, KR, NT, C, H2, batch_norm_strip(PREC, TIER)>(r, blk, lds);
+  else
+    (void)r, (void)blk, (void)lds;
 }
 
 // waves per SIMD the compiler must leave room for: float32 tier 0 mixes 1- and 3-channel

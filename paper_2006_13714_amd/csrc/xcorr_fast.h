@@ -11,7 +11,8 @@
 //
 //  * One workgroup = one 4 x 4 block of references, shared by S waves.  The workgroup
 //    stages the pixel strip covering the block's search windows (all channels, rows
-//    interleaved by channel, compile-time row stride) and the norm strip in LDS once.
+//    interleaved by channel, compile-time row stride) in LDS once; the candidate norms are
+//    read from the norm map a row ahead of use, or (NSTRIP) staged as a norm strip too.
 //    Candidate rows are dealt round-robin to the S waves, so each wave visits the
 //    candidates of every reference in increasing j.
 //  * Matrix tile: 16 references x 16 candidates (a 16-wide row segment).  Operand A
@@ -25,7 +26,7 @@
 //  * Software pipeline: each tile's matrix ops are interleaved with the epilogue
 //    arithmetic of the previous tile and the LDS reads of the next one.
 //  * Metric: Euclidean (Lemma 2) or normalized cross-correlation (Eq. equ:cor, Lemma 1).
-//    For NCC the norm strip holds -1/||X_j|| (times the split forms' post-scale), so the
+//    For NCC the candidate norms become -1/||X_j|| (times the split forms' post-scale), so the
 //    same epilogue multiply-add yields e'' = -<X_i, X_j> / ||X_j||, which orders a
 //    reference's candidates exactly like 2 - 2 NCC; outputs are 2 - 2 NCC = 2 + 2 e'' / ||X_i||.
 //  * Selection (select.h): a bounding sweep over every p1-th candidate row of each wave,
@@ -86,8 +87,9 @@ struct DepthWin {
 // are those of the slabs in `dw` (visited in increasing depth, restaged per slab, one
 // selection state across all of them) and indices are volume positions (z' H + qy) W + qx.
 // NSTRIP: candidate norms staged in LDS with the pixel strip (the layout's norm strip)
-// instead of read from the norm map a row ahead; the single-image kernels read the map,
-// whose smaller LDS footprint is what lets them keep more workgroups per compute unit.
+// instead of read from the norm map a row ahead.  The single-image kernels and the split
+// forms' batch tiers read the map, whose smaller LDS footprint lets more workgroups share a
+// compute unit; the 3D kernels and the float32 batch tiers stage the strip.
 template <class CT, int C, int KR, int NT, bool D3 = false, bool NSTRIP = true>
 __device__ __forceinline__ void fast_block(const float* __restrict__ img,
                                            const float* __restrict__ nrm,
