@@ -339,9 +339,19 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
     post(arith(accp, X, Y, p_tx), p_jrow + kTileN * p_tx + p16);
   };
 
-  // ---- sweep 1: bounding lists over every p1-th row of this wave
+  // ---- sweep 1: bounding lists over every p1-th row of this wave.  In 3D it visits the
+  //      reference's own slab only (still staged): the K-th smallest distance over a subset
+  //      of the window's candidates bounds the K-th smallest over all of them from above,
+  //      which is all the selecting sweep needs, and no slab is restaged for it.
   const int p1 = g.p1_step;
-  over_slabs([&]() __attribute__((always_inline)) {
+  auto over_bound_slabs = [&](auto&& body) __attribute__((always_inline)) {
+    if constexpr (D3) {
+      nm_cur = nrm;
+      jofs = (int)((size_t)(img - dw->vol) / ((size_t)g.H * g.W)) * g.H * g.W;
+    }
+    body();
+  };
+  over_bound_slabs([&]() __attribute__((always_inline)) {
   sweep(qy_lo + wave * p1, S * p1,
         [&](const f4& acc, float X, float Y, int tx) __attribute__((always_inline)) {
           float nt[4];
