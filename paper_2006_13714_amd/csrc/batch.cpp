@@ -40,7 +40,7 @@ static XcBatchKernel batch_kernel(int prec, int kr, int nt, int tier) {
       {{batch_kernel_p0_k1_t2, batch_kernel_p0_k1_t3}, {batch_kernel_p0_k2_t2, batch_kernel_p0_k2_t3}},
       {{batch_kernel_p1_k1_t2, batch_kernel_p1_k1_t3}, {batch_kernel_p1_k2_t2, batch_kernel_p1_k2_t3}},
       {{batch_kernel_p2_k1_t2, batch_kernel_p2_k1_t3}, {batch_kernel_p2_k2_t2, batch_kernel_p2_k2_t3}}};
-  if (prec < 0 || prec > 2 || kr < 1 || kr > 2 || nt < 2 || nt > 3 || tier < 0 || tier > 2)
+  if (prec < 0 || prec > 2 || kr < 1 || kr > 2 || nt < 2 || nt > 3 || tier < 0 || tier > 3)
     return nullptr;
   return table[prec][kr - 1][nt - 2](tier);
 }

@@ -91,9 +91,10 @@ constexpr int fast_max_waves(int prec, int C) { return (prec == 0 && C == 4) ? 4
 constexpr int fast_default_waves(int prec, int C) { return (prec != 0 && C >= 2) ? 8 : 4; }
 
 // Kernel tier of the persistent batch launch for a precision form and channel count, and
-// the largest workgroup (waves) of each tier.
+// the largest workgroup (waves) of each tier: float32 1 channel (tier 3), 2..3 channels (0),
+// 4 channels (1); split forms 1 channel (0), 2..4 channels (2).
 constexpr int batch_tier(int prec, int C) {
-  return prec == 0 ? (C == 4 ? 1 : 0) : (C == 1 ? 0 : 2);
+  return prec == 0 ? (C == 4 ? 1 : (C == 1 ? 3 : 0)) : (C == 1 ? 0 : 2);
 }
 constexpr int batch_max_waves(int tier) { return tier == 2 ? 8 : 4; }
 // Whether a batch tier stages the candidate norms in LDS (else it reads them from each

@@ -10,9 +10,10 @@
 //
 // A kernel's register count and workgroup shape, and with them how many workgroups a
 // compute unit keeps, are shared by every body compiled into it.  The bodies are therefore
-// grouped in tiers of similar shape (batch_tier): float32 tier 0 holds 1..3 channels and
-// tier 1 four channels; the split forms' tier 0 holds one channel and tier 2 two to four
-// channels (8-wave blocks).  A batch runs one persistent launch per tier present.
+// grouped in tiers of similar shape (batch_tier): float32 tier 3 holds one channel, tier 0
+// two and three channels and tier 1 four channels; the split forms' tier 0 holds one
+// channel and tier 2 two to four channels (8-wave blocks).  A batch runs one persistent
+// launch per tier present.
 #pragma once
 
 #include "batch.h"
@@ -39,12 +40,13 @@ __device__ __forceinline__ void batch_tier_block(const BatchXc& r, int blk, unsi
     (void)r, (void)blk, (void)lds;
 }
 
-// waves per SIMD the compiler must leave room for: float32 tier 0 mixes 1- and 3-channel
-// bodies and keeps two; the 8-wave tier needs two per SIMD by construction; the split
-// forms' 1-channel tier with K <= 16 fits three (168 registers, no spills), with larger K
-// it keeps the compiler's choice
+// waves per SIMD the compiler must leave room for: float32 tier 0 (2..3 channels) keeps
+// two; the float32 1-channel tier three (its bodies need under 168 registers); the 8-wave
+// tier needs two per SIMD by construction; the split forms' 1-channel tier with K <= 16
+// fits three (168 registers, no spills), with larger K it keeps the compiler's choice
 constexpr int batch_min_waves(int prec, int tier, int kr) {
   if (tier == 1) return 1;
+  if (tier == 3) return 3;
   if (prec == 0 || tier == 2) return 2;
   return kr == 1 ? 3 : 1;
 }
@@ -100,6 +102,9 @@ static XcBatchKernel batch_tier_kernel(int tier) {
       break;
     case 2:
       if constexpr (PREC != 0) return xcorr_topk_batch<PREC, KR, NT, 2>;
+      break;
+    case 3:
+      if constexpr (PREC == 0) return xcorr_topk_batch<PREC, KR, NT, 3>;
       break;
   }
   return nullptr;
