@@ -8,12 +8,19 @@ the patch-norm box filter (bm_norms) followed by the fused cross-term / distance
 kernel (bm_cross_topk); the two calls together are exactly bm_match.
 
 Output: one JSON line.  Every precision form is timed (plain float32, bfloat16 split,
-float16 split); `value` is ref-patches/s of the reported form (default: the float16 split,
-the fastest form that meets the float32 accuracy bound) over the timed region with the
-inputs already in HBM, and `plain_fp32` gives the plain float32 form beside it.
-`roofline` covers the dominant kernel (the cross-term kernel of the reported form), timed
-with HIP events on its own launch stream; `cpu_baseline` times the FP64 oracle on a bounded
-sample on this host.
+float16 split); `value` is ref-patches/s of the reported form (default: the float16 split)
+over the timed region with the inputs already in HBM, and `plain_fp32` gives the plain
+float32 form beside it.  `roofline` covers the dominant kernel (the cross-term kernel of
+the reported form), timed with HIP events on its own launch stream, against the published
+matrix peak and the peak measured in the same run (`peaks_measured`: a matrix-op loop per
+form and a streaming copy); `executed` adds the matrix/vector pipe utilisation from the
+committed counter summary when it matches the current sources.  The same line carries
+short forms of the other workloads: `batch64` (the 64-image uneven batch, one
+bm_match_batch call per step in each form, and the same images as 64 bm_match calls),
+`serving` (Poisson streams through bm_submit / bm_poll at two request rates, bfloat16
+split; `latency_ms` then holds the request latency of the lower rate), and `cpu_baseline`
+(the FP64 oracle on this host: one core on a bounded sample, all cores on the whole
+image) with `accuracy`, the error of every form against the oracle on a seeded sample.
 
 Other workloads (not the headline line; one JSON line each):
   --workload batch64   64 images of uneven shapes (sides 128..1024, C in {1,3}, P in {6,8})
@@ -35,10 +42,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ref patches/s (top-16, 8x8 patch, 39x39 window) vs plain FP32; p50/p99 latency"
-PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "fp16x3": 2500.0}  # dense matrix-core peaks
-DTYPE = {"fp32": "f32", "bf16x3": "bf16x3->f32", "fp16x3": "f16x3->f32"}
-_FAST = ["xcorr_fast.h", "contract.h", "select.h", "topk.h", "bm_internal.h"]
-KERNEL_SOURCES = {"fp32": _FAST, "bf16x3": _FAST, "fp16x3": _FAST}
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x4": 2500.0, "fp16x3": 2500.0}  # dense matrix-core peaks
+DTYPE = {"fp32": "f32", "bf16x4": "bf16x4->f32", "fp16x3": "f16x3->f32"}
+_FAST = ["xcorr_fast.h", "contract.h", "select.h", "topk.h", "bm_internal.h", "split16.h"]
+KERNEL_SOURCES = {"fp32": _FAST, "bf16x4": _FAST, "fp16x3": _FAST}
 
 
 def source_hash(prec: str) -> str:
@@ -79,8 +86,23 @@ def traffic_from_profile(prec: str, workload: str):
         return None
 
 
-def cpu_baseline(img, sh, budget_s: float):
-    """FP64 oracle on every second reference (bounded by budget_s), refs/s on one core."""
+def _oracle_refs(args):
+    """Worker of the all-core oracle timing: the FP64 oracle on one slice of references."""
+    img, P, s_, Wn, K, refs = args
+    from oracle import bm_oracle as O
+    O.bm(img, P, s_, Wn, K, refs=refs)
+    return len(refs)
+
+
+def cpu_baseline(img, sh, budget_s: float, forms=None):
+    """FP64 oracle timed on this host, and the accuracy of every GPU form against it.
+
+    One core: every second reference in row-major order until budget_s has passed.  All
+    cores: every reference of the image, sliced over a process pool of one worker per
+    available core (workers started and warmed before the timed map).  Accuracy: the
+    oracle's rows for a seeded sample of references, against each form's result (tolerance
+    rule 1e-4 with the 1e-2 (N_i + N_j) floor; set rule)."""
+    import multiprocessing as mp
     import numpy as np
     from oracle import bm_oracle as O
 
@@ -94,10 +116,53 @@ def cpu_baseline(img, sh, budget_s: float):
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "ref-patches/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of {n_ref} references (every 2nd, row-major) of the same "
-                      f"512x512 image, numpy float64 brute force, {dt:.1f} s",
-            "host_threads_available": len(os.sched_getaffinity(0))}
+    out = {"value": done / dt, "unit": "ref-patches/s", "cores": 1, "kind": "oracle",
+           "sample": f"{done} of {n_ref} references (every 2nd, row-major) of the same "
+                     f"512x512 image, numpy float64 brute force, {dt:.1f} s on one core",
+           "host_threads_available": len(os.sched_getaffinity(0))}
+    try:
+        with open("/proc/cpuinfo") as f:
+            out["cpu_model"] = next((l.split(":", 1)[1].strip() for l in f
+                                     if l.startswith("model name")), None)
+    except OSError:
+        pass
+    cores = min(16, len(os.sched_getaffinity(0)))
+    if cores > 1:
+        ctx = mp.get_context("spawn")
+        pool = ctx.Pool(cores)
+        try:
+            refs = np.arange(n_ref)
+            chunks = np.array_split(refs, cores * 4)
+            pool.map_async(_oracle_refs, [(img, sh.patch, sh.stride, sh.window, sh.k, c[:1])
+                                          for c in chunks[:cores]]).get(timeout=120)
+            t0 = time.perf_counter()
+            n = sum(pool.map_async(_oracle_refs, [(img, sh.patch, sh.stride, sh.window, sh.k, c)
+                                                  for c in chunks]).get(timeout=300))
+            dta = time.perf_counter() - t0
+            out["all_cores"] = {"value": n / dta, "unit": "ref-patches/s", "cores": cores,
+                                "sample": f"all {n} references of the image over {cores} "
+                                          f"worker processes, {dta:.1f} s"}
+        except Exception as e:  # a pool problem must not cost the benchmark line
+            out["all_cores"] = {"error": repr(e)}
+        finally:
+            pool.terminate()
+            pool.join()
+    if forms:
+        from tests import parity
+        rng = np.random.default_rng(11)
+        refs = np.unique(np.concatenate([rng.choice(n_ref, 1000, replace=False),
+                                         np.arange(169), np.arange(n_ref - 169, n_ref)]))
+        head = parity.OracleHead(img, sh.patch, sh.stride, sh.window, sh.k, refs=refs)
+        acc = {}
+        for f, (idx, dist) in forms.items():
+            rep = head.check(idx[refs], dist[refs])
+            r = rep.summary()
+            r["within_rule"] = rep.tolerant_mismatch == 0 and rep.order_violations == 0
+            acc[f] = r
+        out["accuracy"] = {"refs": int(len(refs)),
+                           "sample": "1000 seeded references (seed 11) plus the first and "
+                                     "last reference rows", "forms": acc}
+    return out
 
 
 # Untimed warm-up floor per measured form: the device's clocks rise over the first tens of
@@ -291,6 +356,10 @@ def main():
                     help="serving: length of each rate's request stream")
     ap.add_argument("--clients", type=int, default=4,
                     help="serving: client threads sharing the request stream")
+    ap.add_argument("--batch-steps", type=int, default=3,
+                    help="default line: timed calls of the 64-image batch per form (0: skip)")
+    ap.add_argument("--serve-seconds-default", type=float, default=2.0,
+                    help="default line: length of each serving rate's stream (0: skip)")
     args = ap.parse_args()
     global WARM_S
     WARM_S = max(0.0, args.warm_ms) / 1e3
@@ -323,7 +392,7 @@ def main():
         torch.cuda.synchronize()
 
     results = {}
-    for prec in ["fp32", "bf16x3", "fp16x3"]:
+    for prec in ["fp32", "bf16x4", "fp16x3"]:
         results[prec] = run_form(bm, torch, img_t, sh, prec, args.steps, args.warmup)
     # the same workload ranked by normalized cross-correlation (BM_FLAG_NCC)
     ncc = {}
@@ -389,11 +458,123 @@ def main():
             "p50_ms": quantile(sf, 0.5), "p99_ms": quantile(sf, 0.99)}
         for f, (pf, wf, nf, xf, sf, _) in ncc.items()}
     out["volumes"] = volumes(bm, synth, torch, max(3, args.steps // 20), 2)
+    # measured attainable peaks beside the published ones
+    peaks = {f: bm.bm_peak_mfma(f) for f in PEAK_TFLOPS}
+    copy_gbps = bm.bm_peak_copy(1 << 30, 5)
+    out["peaks_measured"] = {"mfma_tflops": peaks, "copy_GBps": copy_gbps,
+                             "published": {"mfma_tflops": PEAK_TFLOPS, "hbm_GBps": 8000.0}}
+    out["roofline"]["peak_measured"] = peaks[prec]
+    out["roofline"]["frac_measured"] = achieved / peaks[prec]
+    for f in forms:
+        forms[f]["roofline_frac_measured"] = forms[f]["roofline_frac"] * PEAK_TFLOPS[f] / peaks[f]
+    counters = mfma_busy_from_profile(prec, w.name)
+    if counters is not None:
+        out["roofline"]["executed"] = counters
+    out["norm"] = {"ms": sum(norm_ms) / len(norm_ms),
+                   "algorithmic_bytes": 4.0 * sh.height * sh.width * sh.channels +
+                   4.0 * (sh.height - sh.patch + 1) * (sh.width - sh.patch + 1)}
+    out["norm"]["GBps"] = out["norm"]["algorithmic_bytes"] / (out["norm"]["ms"] * 1e6)
+    # the uneven 64-image batch and the serving loop, short forms of their own workloads
+    if args.batch_steps > 0:
+        out["batch64"] = batch_summary(bm, synth, torch, args.batch_steps)
+    if args.serve_seconds_default > 0:
+        pool = [w_ for _, w_ in synth.serving_requests(16, 100.0)]
+        sweep = serve_sweep(bm, pool, SERVE_FORM, SERVE_QPS, args.serve_seconds_default,
+                            args.clients)
+        out["serving"] = {"precision": SERVE_FORM, "pool": len(pool), "clients": args.clients,
+                          "sides": "log-uniform 256..2048", "channels": "1..4",
+                          "latency": "submit to results in host memory (PCIe copies included)",
+                          "sweep": sweep}
+        low = sweep[0]
+        out["latency_ms"] = {"p50": low["p50_ms"], "p99": low["p99_ms"],
+                             "kind": f"serving request latency at {low['qps']:.0f} requests/s "
+                                     f"({SERVE_FORM})",
+                             "step_p50": quantile(step_ms, 0.5),
+                             "step_p99": quantile(step_ms, 0.99),
+                             "norm_avg": sum(norm_ms) / len(norm_ms),
+                             "cross_topk_avg": xc_avg_s * 1e3}
     v32 = forms["fp32"]["value"]
     out["plain_fp32"] = {"value": v32, "speedup": value / v32}
     if args.cpu_budget > 0:
-        out["cpu_baseline"] = cpu_baseline(w.image, sh, args.cpu_budget)
+        outs = {f: (r[5][0].cpu().numpy(), r[5][1].cpu().numpy()) for f, r in results.items()}
+        out["cpu_baseline"] = cpu_baseline(w.image, sh, args.cpu_budget, outs)
+        acc = out["cpu_baseline"].get("accuracy", {}).get("forms", {})
+        out["accuracy"] = acc
+        if prec in acc and not acc[prec]["within_rule"]:
+            out["plain_fp32"]["speedup"] = None
+            out["plain_fp32"]["note"] = f"{prec} is outside the 1e-4 rule on the sample"
     print(json.dumps(out), flush=True)
+
+
+SERVE_FORM = "bf16x4"
+SERVE_QPS = [200.0, 800.0]
+
+
+def batch_summary(bm, synth, torch, steps):
+    """The 64-image uneven batch: one bm_match_batch call per step in each form (after an
+    untimed warm-up), and the same images as 64 bm_match calls in the reported form."""
+    ws = synth.uneven_batch(64)
+    ts = [torch.from_numpy(w_.image).to("cuda:0") for w_ in ws]
+    n_ref = sum(w_.shape.n_ref for w_ in ws)
+    flops = sum(2.0 * w_.shape.patch ** 2 * w_.shape.channels *
+                pair_count(w_.shape.height, w_.shape.width, w_.shape.patch, w_.shape.stride,
+                           w_.shape.window) for w_ in ws)
+    stream = torch.cuda.current_stream()
+    res = {"images": len(ws), "n_ref": n_ref, "algorithmic_flops": flops, "forms": {}}
+    for prec in ["fp32", "bf16x4", "fp16x3"]:
+        plans = [bm.cached_plan(bm.make_desc(w_.shape.height, w_.shape.width, w_.shape.channels,
+                                             w_.shape.patch, w_.shape.stride, w_.shape.window,
+                                             w_.shape.k, prec)) for w_ in ws]
+        idxs = [torch.empty((p.n_ref, 16), dtype=torch.int32, device="cuda:0") for p in plans]
+        dists = [torch.empty((p.n_ref, 16), dtype=torch.float32, device="cuda:0") for p in plans]
+        wsb = torch.empty((bm.bm_batch_workspace(plans),), dtype=torch.uint8, device="cuda:0")
+
+        def one_batch():
+            bm.bm_match_batch(plans, ts, idxs, dists, wsb, stream)
+
+        def per_image():
+            for p, t, i, d in zip(plans, ts, idxs, dists):
+                bm.bm_match(p, t, i, d, None, stream)
+
+        entry = {}
+        for name, fn, k in (("batch", one_batch, steps), ("per_image", per_image, 1)):
+            if name == "per_image" and prec != "fp16x3":
+                continue
+            warm(torch, fn, 1)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(k)]
+            for a, b in ev:
+                a.record(stream)
+                fn()
+                b.record(stream)
+            torch.cuda.synchronize()
+            ms = sum(a.elapsed_time(b) for a, b in ev) / k
+            entry[name] = {"ms": ms, "value": n_ref / (ms / 1e3)}
+        entry["roofline_frac"] = flops / (entry["batch"]["ms"] / 1e3) / 1e12 / PEAK_TFLOPS[prec]
+        res["forms"][prec] = entry
+    return res
+
+
+def mfma_busy_from_profile(prec: str, workload: str):
+    """Executed matrix-core utilisation of the cross-term kernel from the committed SQ
+    counter summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"xcorr_{prec}_{workload}_sq_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != source_hash(prec):
+        return None
+    out = {}
+    for k in ("mfma_busy_frac", "valu_busy_frac", "valu_per_tile", "mfma_per_tile"):
+        try:
+            out[k] = float(vals[k])
+        except (KeyError, ValueError):
+            pass
+    return out or None
 
 
 def bench_batch(args, bm, synth, torch):
@@ -408,7 +589,7 @@ def bench_batch(args, bm, synth, torch):
     stream = torch.cuda.current_stream()
     forms = {}
     steps = max(3, min(args.steps, 20))
-    for prec in ["fp32", "bf16x3", "fp16x3"]:
+    for prec in ["fp32", "bf16x4", "fp16x3"]:
         plans = [bm.cached_plan(bm.make_desc(w.shape.height, w.shape.width, w.shape.channels,
                                              w.shape.patch, w.shape.stride, w.shape.window,
                                              w.shape.k, prec)) for w in ws]
@@ -484,17 +665,16 @@ def cpu_baseline_batch(ws, budget_s):
                       f"64-image batch, numpy float64 brute force, {dt:.1f} s"}
 
 
-def bench_serving(args, bm, synth, torch):
-    """Poisson request streams through the serving loop, one rate after another."""
+def serve_sweep(bm, pool, prec, rates, seconds, n_clients):
+    """Poisson request streams through the serving loop, one rate after another: per rate
+    the achieved ref-patches/s and the p50/p99 request latency (submit to results on the
+    host).  Requests replay `pool` cyclically; arrival gaps are Exp(1/QPS), seed QPS + 17."""
     import threading
     import numpy as np
-    pool = [w for _, w in synth.serving_requests(16, 100.0)]
-    prec = args.precision
-    rates = [float(q) for q in args.qps.split(",") if q]
     sweep = []
     for qps in rates:
         rng = np.random.default_rng(int(qps) + 17)
-        n = max(8, int(qps * args.serve_seconds))
+        n = max(8, int(qps * seconds))
         arrivals = np.cumsum(rng.exponential(1.0 / qps, size=n))
         arrivals -= arrivals[0]
         srv = bm.bm_server_create(32 << 30, max_inflight=64, max_queue=4096)
@@ -511,14 +691,14 @@ def bench_serving(args, bm, synth, torch):
                     time.sleep(0.0002)
                     continue
                 for t, (w, d) in items:
-                    st, s = bm.bm_poll(srv, t)
+                    st, s_ = bm.bm_poll(srv, t)
                     if st == bm.BM_OK:
                         with lock:
                             del outstanding[t]
-                        stats.append((s.total_s, s.queue_s, s.device_s, s.n_ref, time.perf_counter()))
+                        stats.append((s_.total_s, s_.queue_s, s_.device_s, s_.n_ref, time.perf_counter()))
                 time.sleep(0.0002)
 
-        # warm: one request of each channel count
+        # warm: one request of each of the first four pool entries
         for w in pool[:4]:
             d = bm.make_desc(w.shape.height, w.shape.width, w.shape.channels, 8, 3, 39, 16, prec)
             t = bm.bm_submit(srv, d, w.image)
@@ -549,7 +729,6 @@ def bench_serving(args, bm, synth, torch):
                         counts["offered"] += w.shape.n_ref
                         counts["rejected"] += 1
 
-        n_clients = args.clients
         cl = [threading.Thread(target=client, args=(c,)) for c in range(n_clients)]
         for t_ in cl:
             t_.start()
@@ -560,16 +739,25 @@ def bench_serving(args, bm, synth, torch):
         stop.set()
         th.join()
         bm.bm_server_destroy(srv)
-        t_end = max(s[4] for s in stats) if stats else t_submitted
-        done_refs = sum(s[3] for s in stats)
-        tot = sorted(s[0] for s in stats)
+        t_end = max(s_[4] for s_ in stats) if stats else t_submitted
+        done_refs = sum(s_[3] for s_ in stats)
+        tot = sorted(s_[0] for s_ in stats)
         sweep.append({"qps": qps, "requests": n, "completed": len(stats), "rejected": rejected,
                       "offered_refs_per_s": offered / max(arrivals[-1], 1e-9),
                       "achieved_refs_per_s": done_refs / (t_end - t_start),
                       "p50_ms": 1e3 * quantile(tot, 0.5), "p99_ms": 1e3 * quantile(tot, 0.99),
-                      "queue_p50_ms": 1e3 * quantile(sorted(s[1] for s in stats), 0.5),
-                      "device_p50_ms": 1e3 * quantile(sorted(s[2] for s in stats), 0.5)})
+                      "queue_p50_ms": 1e3 * quantile(sorted(s_[1] for s_ in stats), 0.5),
+                      "device_p50_ms": 1e3 * quantile(sorted(s_[2] for s_ in stats), 0.5)})
         print(json.dumps({"serving_level": sweep[-1]}), file=sys.stderr, flush=True)
+    return sweep
+
+
+def bench_serving(args, bm, synth, torch):
+    """Poisson request streams through the serving loop, one rate after another."""
+    pool = [w for _, w in synth.serving_requests(16, 100.0)]
+    prec = args.precision
+    rates = [float(q) for q in args.qps.split(",") if q]
+    sweep = serve_sweep(bm, pool, prec, rates, args.serve_seconds, args.clients)
     best = max(sweep, key=lambda r: r["achieved_refs_per_s"])
     # device capacity for this request mix: the pool as one resident batch, no host copies
     plans = [bm.cached_plan(bm.make_desc(w.shape.height, w.shape.width, w.shape.channels, 8, 3,

@@ -51,12 +51,19 @@ typedef int32_t bm_status;
 
 /* Arithmetic of the cross term <X_i, X_j>.  Norms and the distance assembly are float32
  * in every form.  The split forms write x = hi + lo (hi = round(x), lo = round(x - hi)) and
- * accumulate hi*hi + hi*lo + lo*hi in float32 on the matrix cores. */
+ * accumulate the products of the parts in float32 on the matrix cores. */
 #define BM_PREC_FP32 0      /* float32 products, float32 accumulation                 */
-#define BM_PREC_BF16X3 1    /* bfloat16 hi/lo split, three products                   */
+#define BM_PREC_BF16X4 1    /* bfloat16 hi/lo split, all four products hi*hi + hi*lo +
+                               lo*hi + lo*lo, i.e. the exact cross term of the image
+                               rounded to hi + lo (16 significant bits); the norm map of
+                               such a plan (bm_norms) holds the norms of the same rounded
+                               values, so Lemma 2's cancellation is exact for the rounded
+                               patches and the result differs from the float32 one only
+                               by the distance between rounded and original patches     */
 #define BM_PREC_FP16X3 2    /* float16 hi/lo split after a power-of-two pre-scale,
                                chosen per 4 x 4 block of references from the largest
-                               |x| around it (a property of the image, not of the call) */
+                               |x| around it (a property of the image, not of the call);
+                               three products hi*hi + hi*lo + lo*hi (22 significant bits) */
 
 /* bm_desc.flags */
 #define BM_FLAG_CENTER 1u   /* subtract a per-channel mean before the cross term (the
@@ -117,7 +124,9 @@ bm_status bm_match(bm_plan_t plan, const float* d_img, int32_t* d_idx, float* d_
 
 /* Patch-norm map alone (the box filter, h_X (.) h_X of Sec. III-B): d_norm receives
  * (H-P+1)*(W-P+1) floats, row-major (3D plans: one such map per slab z = 0..q-d, stacked by
- * z, each the norms of the d-plane blocks at that depth).  It also writes the plan's own workspace (centring
+ * z, each the norms of the d-plane blocks at that depth).  BM_PREC_BF16X4 plans: the norms
+ * of the image rounded to the bfloat16 hi + lo split (each value x becomes hi + lo).  It
+ * also writes the plan's own workspace (centring
  * constants, and the per-tile maxima of |x| that BM_PREC_FP16X3 reads), which the next
  * bm_cross_topk on the same plan consumes: such pairs on one plan must not overlap in
  * time.  Asynchronous on `stream`. */
@@ -212,6 +221,10 @@ typedef struct {
   int64_t hbm_budget_bytes;  /* device bytes the server may hold for admitted requests */
   int32_t max_inflight;      /* admitted (device-resident) requests at most            */
   int32_t max_queue;         /* queued, not yet admitted requests at most               */
+  int32_t max_step;          /* requests launched together as one step at most (the
+                                work of one batch launch); 0 = 8.  A step also takes at
+                                most half of max_inflight (at least 1), so that a next step
+                                can be admitted while one runs                             */
 } bm_server_cfg;
 
 typedef struct {

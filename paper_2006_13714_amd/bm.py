@@ -25,9 +25,9 @@ BM_ECANCELED = -7
 BM_ENOTSUP = -8
 
 BM_PREC_FP32 = 0
-BM_PREC_BF16X3 = 1
+BM_PREC_BF16X4 = 1
 BM_PREC_FP16X3 = 2
-PRECISIONS = {"fp32": BM_PREC_FP32, "bf16x3": BM_PREC_BF16X3, "fp16x3": BM_PREC_FP16X3}
+PRECISIONS = {"fp32": BM_PREC_FP32, "bf16x4": BM_PREC_BF16X4, "fp16x3": BM_PREC_FP16X3}
 
 BM_FLAG_CENTER = 1
 BM_FLAG_NCC = 2
@@ -42,7 +42,7 @@ class bm_desc(C.Structure):
 
 class bm_server_cfg(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("max_inflight", C.c_int32),
-                ("max_queue", C.c_int32)]
+                ("max_queue", C.c_int32), ("max_step", C.c_int32)]
 
 
 class bm_request_stats(C.Structure):
@@ -85,6 +85,8 @@ _SIGS = {
     "bm_server_destroy": (C.c_int32, [C.c_void_p]),
     "bm_autotune": (C.c_int32, [C.POINTER(bm_desc), C.c_void_p, C.c_int32, C.c_char_p, C.c_int32]),
     "bm_plan_config": (C.c_int32, [C.c_void_p, C.c_char_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "bm_peak_mfma": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
+    "bm_peak_copy": (C.c_int32, [C.c_int64, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
     "bm_status_str": (C.c_char_p, [C.c_int32]),
     "bm_last_error": (C.c_char_p, []),
 }
@@ -254,8 +256,24 @@ def bm_plan_config(plan: Plan):
     return out.value.decode(), src.value
 
 
-def bm_server_create(hbm_budget_bytes: int, max_inflight: int = 64, max_queue: int = 4096) -> int:
-    cfg = bm_server_cfg(hbm_budget_bytes, max_inflight, max_queue)
+def bm_peak_mfma(precision, iterations: int = 20000, stream=None) -> float:
+    """Measured matrix-core rate (TFLOP/s) of the instruction a precision form issues."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    out = C.c_double()
+    _check(lib().bm_peak_mfma(prec, iterations, _stream(stream), C.byref(out)), "bm_peak_mfma")
+    return out.value
+
+
+def bm_peak_copy(nbytes: int = 1 << 30, repeats: int = 5, stream=None) -> float:
+    """Measured streaming device-copy rate (GB/s of bytes read plus written)."""
+    out = C.c_double()
+    _check(lib().bm_peak_copy(nbytes, repeats, _stream(stream), C.byref(out)), "bm_peak_copy")
+    return out.value
+
+
+def bm_server_create(hbm_budget_bytes: int, max_inflight: int = 64, max_queue: int = 4096,
+                     max_step: int = 0) -> int:
+    cfg = bm_server_cfg(hbm_budget_bytes, max_inflight, max_queue, max_step)
     h = C.c_void_p()
     _check(lib().bm_server_create(C.byref(cfg), C.byref(h)), "bm_server_create")
     return h.value
@@ -292,6 +310,19 @@ def bm_server_destroy(server: int):
 _plan_cache: dict = {}
 
 
+def _call_workspace(plan: Plan, device, stream):
+    """A workspace of plan.workspace_bytes for one call, from torch's allocator on the
+    call's stream, so calls of one cached plan on different streams never share the
+    plan's own workspace (norm map and auxiliary slots)."""
+    import torch
+    if plan.workspace_bytes <= 0:
+        return None
+    if stream is None or isinstance(stream, int):
+        return torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=device)
+    with torch.cuda.stream(stream):
+        return torch.empty((plan.workspace_bytes,), dtype=torch.uint8, device=device)
+
+
 def cached_plan(desc: bm_desc) -> Plan:
     key = tuple(getattr(desc, f) for f, _ in bm_desc._fields_)
     p = _plan_cache.get(key)
@@ -316,7 +347,7 @@ def match3d(vol, patch: int, patch_depth: int, stride: int, window: int, window_
                                      patch_depth, window_depth))
     idx = torch.empty((plan.n_ref, k), dtype=torch.int32, device=vol.device)
     dist = torch.empty((plan.n_ref, k), dtype=torch.float32, device=vol.device)
-    bm_match(plan, vol, idx, dist, None, stream)
+    bm_match(plan, vol, idx, dist, _call_workspace(plan, vol.device, stream), stream)
     return idx, dist
 
 
@@ -334,7 +365,7 @@ def nlm(img, patch: int, stride: int, window: int, b: float, plan: Plan | None =
         plan = cached_plan(make_desc(H, W, Cn, patch, stride, window, 16, "fp32", 0))
     out = torch.empty((plan.n_ref, Cn, patch, patch), dtype=torch.float32, device=img.device)
     theta = torch.empty((plan.n_ref,), dtype=torch.float32, device=img.device)
-    bm_nlm(plan, img, b, out, theta, None, stream)
+    bm_nlm(plan, img, b, out, theta, _call_workspace(plan, img.device, stream), stream)
     return theta, out
 
 
@@ -348,9 +379,9 @@ def match(img, patch: int, stride: int, window: int, k: int, precision="fp32", f
         raise ValueError("img must be a float32 tensor on the GPU")
     img = img.contiguous()
     Cn, H, W = img.shape
-    if plan is None:  # cached: a plan's workspace must outlive the asynchronous launch
+    if plan is None:
         plan = cached_plan(make_desc(H, W, Cn, patch, stride, window, k, precision, flags))
     idx = torch.empty((plan.n_ref, k), dtype=torch.int32, device=img.device)
     dist = torch.empty((plan.n_ref, k), dtype=torch.float32, device=img.device)
-    bm_match(plan, img, idx, dist, None, stream)
+    bm_match(plan, img, idx, dist, _call_workspace(plan, img.device, stream), stream)
     return idx, dist

@@ -237,9 +237,26 @@ bm_status bm_plan(const bm_desc* desc, bm_plan_t* out) {
       st = fail(BM_ENOTSUP, "3D search needs patch 3..8 (5..8 split), K <= 32 and "
                             "3*stride + window <= 48");
     } else {
-      // the 3D kernel stages candidate norms in LDS with each slab's strip
+      // the 3D kernel stages candidate norms in LDS with each slab's strip; the 2D
+      // configuration was sized without that strip, so if it no longer fits, take the
+      // largest block (waves, then buffer capacity) at or below it that does
       XcGeom g3;
       fill_geom(p->desc, p->cfg.wy, 1, p->cfg.cap, true, g3, true);
+      if (g3.lds_bytes > max_lds) {
+        bool found = false;
+        for (int ws = p->cfg.wy; ws >= 1 && !found; ws = ws > 1 ? ws / 2 : 0)
+          for (int cap : {p->cfg.cap, 48, 32}) {
+            if (cap > p->cfg.cap || (ws == p->cfg.wy && cap == p->cfg.cap)) continue;
+            fill_geom(p->desc, ws, 1, cap, true, g3, true);
+            if (g3.lds_bytes <= max_lds) {
+              p->cfg.wy = ws;
+              p->cfg.cap = cap;
+              found = true;
+              break;
+            }
+          }
+        if (!found) fill_geom(p->desc, p->cfg.wy, 1, p->cfg.cap, true, g3, true);
+      }
       g3.p1_step = p->cfg.p1;
       if (g3.lds_bytes > max_lds) {
         st = fail(BM_ENOTSUP, "3D tile needs %d bytes of LDS (limit %d)", g3.lds_bytes, max_lds);

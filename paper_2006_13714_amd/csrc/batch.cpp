@@ -265,7 +265,8 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
     r.out = e[b].nrm;
     r.centers = e[b].aux.centers;
     r.amax = e[b].aux.amax;
-    r.g = NormGeom{p.geom.H, p.geom.W, p.geom.C, p.geom.P, p.geom.Hv, p.geom.Wv};
+    r.g = NormGeom{p.geom.H, p.geom.W, p.geom.C, p.geom.P, p.geom.Hv, p.geom.Wv,
+                   p.desc.precision == BM_PREC_BF16X4 ? 1 : 0};
     int tx, ty;
     norm_tiles(r.g, &tx, &ty);
     r.tile_begin = tiles;
@@ -300,6 +301,7 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
     if (he != hipSuccess) return hip_fail(he, "persistent kernel set-up");
     if (per_cu < 1) return fail(BM_ENOTSUP, "persistent kernel does not fit a compute unit");
     const int grid = std::min(g.items, per_cu * n_cu);
+    (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
     hipLaunchKernelGGL(k, dim3(grid), dim3(64 * g.ws), g.lds, s,
                        reinterpret_cast<const BatchXc*>(dh + xc_off) + g.rec_off,
                        (int)g.members.size(), g.items, counters + q);

@@ -105,6 +105,9 @@ constexpr bool batch_norm_strip(int prec, int tier) { return (void)tier, prec ==
 
 struct NormGeom {
   int H, W, C, P, Hv, Wv;
+  int round_bf16;  // 1: norms of the values rounded to the bfloat16 hi + lo split (the
+                   // norms the bfloat16 split form's distance assembly pairs with its
+                   // cross term); 0: of the values themselves
 };
 
 // Group gather / aggregation geometry (one plan's image, patch and K).

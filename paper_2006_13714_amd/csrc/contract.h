@@ -10,8 +10,12 @@
 //  CtF32   float32 products, v_mfma_f32_16x16x4f32; a step covers a 2 x 2 pixel block of one
 //          channel (lane group g holds pixel (g/2, g%2) of the block).
 //  CtSplit x = hi + lo split in bfloat16 (FP16 = false) or float16 after a power-of-two
-//          pre-scale (FP16 = true); three products hi*hi + hi*lo + lo*hi per element on
-//          v_mfma_f32_16x16x32_{bf16,f16}.  A lane holds a 4-row x 2-column pixel block per
+//          pre-scale (FP16 = true) on v_mfma_f32_16x16x32_{bf16,f16}.  float16: three
+//          products hi*hi + hi*lo + lo*hi per element (22 significant bits; the dropped
+//          lo*lo is below float32 rounding).  bfloat16: all four products, so the cross term
+//          is the exact product of the rounded values hi + lo (16 significant bits), which
+//          the distance assembly pairs with the norms of the same rounded values
+//          (split16.h).  A lane holds a 4-row x 2-column pixel block per
 //          32-element block; the strip stores, per pixel x, the 32-bit word (v[x], v[x+1])
 //          of 16-bit parts, so every read is aligned.  The hi parts form one plane (rows:
 //          image row, then channel) and the lo parts a second plane SH * C rows later, so the
@@ -23,6 +27,7 @@
 #include <stdint.h>
 
 #include "bm_internal.h"
+#include "split16.h"
 
 namespace bmk {
 
@@ -38,7 +43,9 @@ struct CtF32 {
   static constexpr int ROWS = C;              // strip rows per image row
   static constexpr int CRS = ROWS * RW;       // words per image row
   static constexpr int NS = C * H2 * H2;      // steps (matrix ops) per tile
+  static constexpr int NA = NS;               // operand-A registers
   static constexpr int NB = NS;               // operand-B registers per tile
+  static constexpr int NACC = NS >= 32 ? 4 : 2;  // accumulators of the chain
   static constexpr bool kScaled = false;
   static constexpr bool kSplit = false;
   using AReg = float;
@@ -107,13 +114,19 @@ struct CtF32 {
   __device__ static f4 chain_and_load(const AReg (&A)[NS], const float (&cur)[NB],
                                       float (&nxt)[NB], const uint32_t* strip, int nb, int = 0) {
     const float* s = reinterpret_cast<const float*>(strip);
-    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    // NACC independent accumulators over interleaved steps, added pairwise at the end:
+    // each partial sum stays a fraction of the cross term, so its roundings are smaller
+    // than those of one accumulator running through all NS steps
+    f4 acc[NACC];
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A[t], cur[t], acc, 0, 0, 0);
+      acc[t % NACC] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[t], cur[t], acc[t % NACC], 0, 0, 0);
       nxt[t] = s[nb + off(t)];
     }
-    return acc;
+    if constexpr (NACC == 4) return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    else return acc[0] + acc[1];
   }
 
   __device__ static void schedule() {
@@ -127,11 +140,6 @@ struct CtF32 {
 };
 
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t bf16_rne_bits(float v) {
-  const uint32_t b = __float_as_uint(v);
-  return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
-}
-
 template <bool FP16>
 __device__ __forceinline__ void split2(float v, uint32_t& hi, uint32_t& lo) {
   if constexpr (FP16) {
@@ -155,7 +163,9 @@ struct CtSplit {
   static constexpr int NRB = (PE + 3) / 4;    // 4-row blocks
   static constexpr int NCB = (PE + 7) / 8;    // 8-column blocks
   static constexpr int NKB = C * NRB * NCB;   // 32-element blocks
-  static constexpr int NS = 3 * NKB;          // matrix ops per tile
+  static constexpr bool kLL = !FP16;          // bfloat16: lo*lo as a fourth product
+  static constexpr int NS = (kLL ? 4 : 3) * NKB;  // matrix ops per tile
+  static constexpr int NA = 2 * NKB;          // operand-A vectors (hi, lo per block)
   static constexpr int NB = 2 * NKB;          // operand-B vectors per tile (hi, lo per block)
   static constexpr bool kScaled = FP16;
   static constexpr bool kSplit = true;
@@ -268,10 +278,12 @@ struct CtSplit {
                                       u4 (&nxt)[NB], const uint32_t* strip, int nb, int lo) {
     const uint32_t* sh = strip + nb;
     const uint32_t* sl = strip + nb + lo;
+    // The small products first, then hi * hi: the accumulator only reaches the size of the
+    // cross term in the last NKB ops, so fewer roundings happen at that size.
     f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int b = 0; b < NKB; ++b) {
-      acc = mfma(A[2 * b], cur[2 * b], acc);          // hi * hi
+      if constexpr (kLL) acc = mfma(A[2 * b + 1], cur[2 * b + 1], acc);  // lo * lo
       acc = mfma(A[2 * b], cur[2 * b + 1], acc);      // hi * lo
       acc = mfma(A[2 * b + 1], cur[2 * b], acc);      // lo * hi
 #pragma unroll
@@ -279,6 +291,8 @@ struct CtSplit {
 #pragma unroll
       for (int i = 0; i < 4; ++i) nxt[2 * b + 1][i] = sl[woff(b, i)];
     }
+#pragma unroll
+    for (int b = 0; b < NKB; ++b) acc = mfma(A[2 * b], cur[2 * b], acc);  // hi * hi
     return acc;
   }
 

@@ -363,6 +363,7 @@ hipError_t launch_gather(const float* img, const int32_t* idx, float* groups, co
   const int ib = items_per_block(g.C * g.P * g.P);
   const long long blocks = (items + ib - 1) / ib;
   if (blocks >= (1ll << 31)) return hipErrorInvalidValue;
+  (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
   hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(kGroupThreads), 0, s, img, idx,
                      groups, g, ib);
   return hipGetLastError();
@@ -402,12 +403,14 @@ hipError_t launch_aggregate(const float* groups, const int32_t* idx, float* out,
                                                a256(4ll * g.H * g.W));
   const long long n_acc = (long long)g.C * g.H * g.W;
   const long long total = g.n_ref * g.K * (long long)g.C * g.P * g.P;
+  (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
   hipLaunchKernelGGL(agg_zero_kernel, dim3(grid_for(n_acc)), dim3(kGroupThreads), 0, s, acc, cnt,
                      slot, n_acc, (long long)g.H * g.W);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (total > 0) {
     const int gmax = grid_for(total / 4 + 1) < 2048 ? grid_for(total / 4 + 1) : 2048;
+    (void)hipGetLastError();
     if ((reinterpret_cast<uintptr_t>(groups) & 15) == 0)
       hipLaunchKernelGGL(agg_absmax_kernel<true>, dim3(gmax), dim3(kGroupThreads), 0, s, groups,
                          total, slot);
@@ -418,17 +421,20 @@ hipError_t launch_aggregate(const float* groups, const int32_t* idx, float* out,
     if (g.tb > 0) {
       const long long tiles = (long long)g.ntx * g.nty;
       const int lds = g.th * g.tw * 8;
+      (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
       hipLaunchKernelGGL(agg_tile_kernel<kGroupThreads>, dim3((unsigned)tiles, (unsigned)g.C),
                          dim3(kGroupThreads), lds, s, groups, idx, acc, cnt, slot, g);
     } else {
       const int ib = items_per_block(g.C * g.P * g.P);
       const long long blocks = (g.n_ref * g.K + ib - 1) / ib;
       if (blocks >= (1ll << 31)) return hipErrorInvalidValue;
+      (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
       hipLaunchKernelGGL(agg_deposit_kernel, dim3((unsigned)blocks), dim3(kGroupThreads), 0, s,
                          groups, idx, acc, cnt, slot, g, ib);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
   hipLaunchKernelGGL(agg_normalise_kernel, dim3((g.W + kNX - 1) / kNX, (g.H + kNY - 1) / kNY),
                      dim3(kGroupThreads), 0, s, acc, cnt, slot, out, g);
   return hipGetLastError();

@@ -50,6 +50,7 @@ hipError_t launch_nlm(const float* img, const float* nrm, float* patch, float* t
     }
   }
   const float kexp = -1.4426950408889634f / (b * b);  // exp(-d / b^2) = exp2(d * kexp)
+  (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
   hipLaunchKernelGGL(k, dim3(g.nwg_total), dim3(64 * g.WS), lds, stream, img, nrm, patch, theta,
                      fast_geom(g), kexp);
   return hipGetLastError();

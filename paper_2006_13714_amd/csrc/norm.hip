@@ -13,6 +13,9 @@
 // carried in float64, so every output is the float32 rounding of the exact norm.  Each
 // input element is read once from HBM (halos come from L2) and each output written once.
 //
+// For the bfloat16 split form the staged values are first rounded to hi + lo (split16.h),
+// so the map holds the norms of the rounded image that the form's cross term multiplies.
+//
 // Each tile also writes max |x - center_c| over its staged window (all channels) to a
 // per-tile map when asked; the float16 split form takes its per-block pre-scale from it.
 //
@@ -22,6 +25,7 @@
 
 #include "batch.h"
 #include "bm_internal.h"
+#include "split16.h"
 
 namespace bmk {
 
@@ -55,6 +59,7 @@ __device__ __forceinline__ void norm_tile(const float* __restrict__ img, float* 
       const int y = oy0 + rr, x = ox0 + xx;
       float v = 0.f;
       if (y < g.H && x < g.W) v = plane[(size_t)y * g.W + x] - cc;
+      if (g.round_bf16) v = bf16_split_value(v);
       sh.tile[rr][xx] = v;
       vmax = fmaxf(vmax, fabsf(v));
     }
@@ -125,6 +130,7 @@ hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const fl
                        float* amax, hipStream_t stream) {
   int tx, ty;
   norm_tiles(g, &tx, &ty);
+  (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
   hipLaunchKernelGGL(norm_box_kernel, dim3(tx, ty), dim3(256), 0, stream, img, out, g, centers,
                      amax);
   return hipGetLastError();
@@ -133,6 +139,7 @@ hipError_t launch_norm(const float* img, float* out, const NormGeom& g, const fl
 hipError_t launch_norm_batch(const BatchNorm* d_items, int n, int total_tiles,
                              unsigned* d_counters, int n_counters, hipStream_t stream) {
   if (n < 1 || total_tiles < 1 || n_counters > 256) return hipErrorInvalidValue;
+  (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
   hipLaunchKernelGGL(norm_box_batch_kernel, dim3(total_tiles), dim3(256), 0, stream, d_items, n,
                      d_counters, n_counters);
   return hipGetLastError();

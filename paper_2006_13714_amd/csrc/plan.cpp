@@ -232,7 +232,7 @@ bm_status run_norms(const bm_plan_s& p, const float* d_img, float* d_norm, const
     e = launch_centers(d_img, g.C, g.H, g.W, aux.centers, s);
     if (e != hipSuccess) return hip_fail(e, "centring launch");
   }
-  NormGeom ng{g.H, g.W, g.C, g.P, g.Hv, g.Wv};
+  NormGeom ng{g.H, g.W, g.C, g.P, g.Hv, g.Wv, p.desc.precision == BM_PREC_BF16X4 ? 1 : 0};
   // 3D: one norm map (and max map) per d-plane slab, stacked by depth
   const size_t plane = (size_t)g.H * g.W, nmap = (size_t)g.Hv * g.Wv;
   const size_t tiles = (size_t)norm_tile_count(p.desc);

@@ -166,15 +166,32 @@ struct RefSelect {
   __device__ __forceinline__ void write_col(int v, int* out_idx, float* out_dist, size_t ref,
                                             bool valid) const {
     if (!valid) return;
+    float o[KR];
+    int oj[KR];
+#pragma unroll
+    for (int q = 0; q < KR; ++q) {
+      const bool none = Lj[v][q] == kNoIndex;
+      o[q] = none ? INFINITY
+                  : (ncc ? fminf(fmaxf(fmaf(outk[v], Ld[v][q], 2.f), 0.f), 4.f)
+                         : fmaxf(Ld[v][q], 0.f));
+      oj[q] = Lj[v][q];
+    }
+    // The outputs are a monotone map of the keys (NCC: 2 - 2 NCC; Euclidean: the clamp at
+    // 0), but the map can give two distinct keys the same output (NCC rounding and clamp,
+    // negative Euclidean keys); sorting the outputs by (value, index) then puts the
+    // smaller index first, as the output order requires.  Euclidean lists without a
+    // negative key map one to one and skip it.
+    bool neg = false;
+#pragma unroll
+    for (int q = 0; q < KR; ++q) neg |= Ld[v][q] < 0.f;
+    if (ncc || vote(neg)) sort_list<KR>(o, oj, p16);
 #pragma unroll
     for (int q = 0; q < KR; ++q) {
       const int e = 16 * q + p16;
       if (e < K) {
-        const bool none = Lj[v][q] == kNoIndex;
-        const float o = ncc ? fminf(fmaxf(fmaf(outk[v], Ld[v][q], 2.f), 0.f), 4.f)
-                            : fmaxf(Ld[v][q], 0.f);
-        out_idx[ref * K + e] = none ? -1 : Lj[v][q];
-        out_dist[ref * K + e] = none ? INFINITY : o;
+        const bool none = oj[q] == kNoIndex;
+        out_idx[ref * K + e] = none ? -1 : oj[q];
+        out_dist[ref * K + e] = none ? INFINITY : o[q];
       }
     }
   }

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <memory>
 #include <new>
+#include <string>
 
 #include "batch_run.h"
 #include "plan.h"
@@ -167,6 +168,8 @@ class HipExecutor : public Executor {
     for (hipStream_t st : {in_, comp_[0], comp_[1], out_}) (void)hipStreamSynchronize(st);
   }
 
+  std::string last_message() override { return last_error(); }
+
   bm_status step_status(Step* s) override {
     auto* ss = static_cast<StepState*>(s->exec.get());
     return ss ? ss->status : BM_OK;
@@ -196,7 +199,8 @@ extern "C" {
 bm_status bm_server_create(const bm_server_cfg* cfg, bm_server_t* out) {
   if (!cfg || !out) return fail(BM_EINVAL, "NULL argument");
   *out = nullptr;
-  if (cfg->hbm_budget_bytes < (1 << 20) || cfg->max_inflight < 1 || cfg->max_queue < 1)
+  if (cfg->hbm_budget_bytes < (1 << 20) || cfg->max_inflight < 1 || cfg->max_queue < 1 ||
+      cfg->max_step < 0 || cfg->max_step > 64)
     return fail(BM_EINVAL, "server configuration out of range");
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
@@ -233,9 +237,12 @@ bm_status bm_submit(bm_server_t srv, const bm_desc* desc, const float* host_img,
 bm_status bm_poll(bm_server_t srv, uint64_t ticket, int32_t* host_idx, float* host_dist,
                   bm_request_stats* stats) {
   if (!srv) return fail(BM_EINVAL, "NULL server");
-  bm_status st = srv->sch->poll(ticket, host_idx, host_dist, stats);
+  std::string why;
+  bm_status st = srv->sch->poll(ticket, host_idx, host_dist, stats, &why);
   if (st == BM_ENOTFOUND) return fail(st, "unknown or retired ticket %llu", (unsigned long long)ticket);
-  if (st != BM_OK && st != BM_EAGAIN) return fail(st, "request %llu did not complete", (unsigned long long)ticket);
+  if (st != BM_OK && st != BM_EAGAIN)
+    return fail(st, "request %llu did not complete%s%s", (unsigned long long)ticket,
+                why.empty() ? "" : ": ", why.c_str());
   return st;
 }
 

@@ -28,6 +28,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -109,6 +110,7 @@ struct Request {
   ReqState state = ReqState::Queued;
   bool cancel_requested = false;
   bm_status status = BM_OK;
+  std::string message;         // why it failed (the executor's message at the time)
   double t_submit = 0, t_admit = 0, t_done = 0;
   std::shared_ptr<void> exec;  // executor's per-request state (plan)
 };
@@ -131,6 +133,7 @@ class Executor {
   virtual bool step_done(Step* s) = 0;                      // non-blocking completion test
   virtual void wait_step(Step* s) = 0;                      // blocking
   virtual bm_status step_status(Step*) { return BM_OK; }    // after completion
+  virtual std::string last_message() { return ""; }         // text of the last failure
 };
 
 inline double now_s() {
@@ -192,7 +195,8 @@ class Scheduler {
   }
 
   // A finished request is retired under the lock and its results copied outside it.
-  bm_status poll(uint64_t t, int32_t* idx, float* dist, bm_request_stats* st) {
+  bm_status poll(uint64_t t, int32_t* idx, float* dist, bm_request_stats* st,
+                 std::string* message = nullptr) {
     std::unique_ptr<Request> r;
     {
       std::unique_lock<std::mutex> lk(mu_);
@@ -217,6 +221,7 @@ class Scheduler {
       }
     } else {
       s = r->state == ReqState::Cancelled ? BM_ECANCELED : r->status;
+      if (message) *message = r->message;
     }
     if (r->host_off >= 0) {
       std::unique_lock<std::mutex> lk(mu_);
@@ -330,11 +335,22 @@ class Scheduler {
   // 2. admission (lock held): arrival order, stop at the first request that does not fit.
   //    The step header is reserved first, sized for the most requests this step can take.
   void admit(Step* step) {
-    const int64_t step_cap = std::max<int64_t>(1, std::min<int64_t>(kMaxStep, cfg_.max_inflight / 2));
+    const int64_t max_step = cfg_.max_step > 0 ? cfg_.max_step : kMaxStep;
+    const int64_t step_cap = std::max<int64_t>(1, std::min<int64_t>(max_step, cfg_.max_inflight / 2));
     const int64_t room = std::min<int64_t>(std::min<int64_t>((int64_t)queue_.size(), step_cap),
                                            cfg_.max_inflight - admitted_);
     if (room <= 0) return;
-    if (!dev_.alloc(ex_->step_header_bytes((int)room), &step->hdr_off)) return;
+    if (!admit_some(step, room) && room > 1) {
+      // the header for `room` requests may be what leaves the head out: a step of one
+      // needs the smallest header
+      admit_some(step, 1);
+    }
+  }
+
+  // Reserve a header for up to `room` requests, then admit in arrival order while they
+  // fit; false (nothing reserved) if not even the head fits.
+  bool admit_some(Step* step, int64_t room) {
+    if (!dev_.alloc(ex_->step_header_bytes((int)room), &step->hdr_off)) return false;
     std::vector<Request*> take;
     while (!queue_.empty() && (int64_t)take.size() < room) {
       Request* r = queue_.front();
@@ -355,9 +371,10 @@ class Scheduler {
     if (take.empty()) {
       dev_.release(step->hdr_off);
       step->hdr_off = -1;
-      return;
+      return false;
     }
     step->reqs = std::move(take);
+    return true;
   }
 
   void fail_request(Request* r, bm_status s) {
@@ -367,6 +384,7 @@ class Scheduler {
     if (r->state == ReqState::Admitted) --admitted_;
     r->state = r->cancel_requested ? ReqState::Cancelled : ReqState::Failed;
     r->status = s;
+    r->message = ex_->last_message();
     r->t_done = now_s();
   }
 

@@ -42,6 +42,7 @@ center_kernel(const float* __restrict__ img, int C, int HW, float* __restrict__ 
 
 hipError_t launch_centers(const float* img, int C, int H, int W, float* centers,
                           hipStream_t stream) {
+  (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
   hipLaunchKernelGGL(center_kernel, dim3(1), dim3(kStatsThreads), 0, stream, img, C, H * W,
                      centers);
   return hipGetLastError();

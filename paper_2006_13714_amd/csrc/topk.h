@@ -121,6 +121,28 @@ __device__ __forceinline__ void merge_batch(float (&Ld)[KR], int (&Lj)[KR], floa
   Lj[KR - 1] = cj;
 }
 
+// Sort a list of 16 * KR entries (KR <= 2) by (d, j) ascending: element e = 16 r + p in
+// register r of lane p.  Used where a monotone map of sorted keys can create equal values
+// whose indices are then out of order.
+template <int KR>
+__device__ __forceinline__ void sort_list(float (&d)[KR], int (&j)[KR], int p) {
+  static_assert(KR == 1 || KR == 2, "lists of 16 or 32");
+  if constexpr (KR == 1) {
+    sort16(d[0], j[0], p, true);
+  } else {
+    sort16(d[0], j[0], p, true);
+    sort16(d[1], j[1], p, false);
+    // ascending against descending: the lane-wise smaller entries are the 16 smallest,
+    // and both halves are bitonic
+    const bool lt = key_less(d[0], j[0], d[1], j[1]);
+    const float lo_d = lt ? d[0] : d[1], hi_d = lt ? d[1] : d[0];
+    const int lo_j = lt ? j[0] : j[1], hi_j = lt ? j[1] : j[0];
+    d[0] = lo_d, j[0] = lo_j, d[1] = hi_d, j[1] = hi_j;
+    bitonic_merge16(d[0], j[0], p);
+    bitonic_merge16(d[1], j[1], p);
+  }
+}
+
 // ---- distance-only networks (no indices): used to bound the K-th distance ------------
 // Distances only: min or max by a compare and a select (no NaN ever reaches these networks,
 // so the min/max of the IEEE functions and their operand canonicalisation are not needed).

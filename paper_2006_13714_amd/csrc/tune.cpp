@@ -204,6 +204,7 @@ bm_status bm_autotune(const bm_desc* desc, const float* d_img, int32_t reps, cha
       (void)hipGetLastError();
       return fail(BM_ENOMEM, "autotune image");
     }
+    (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
     hipLaunchKernelGGL(tune_image_kernel, dim3((unsigned)((img_elems + 255) / 256)), dim3(256), 0,
                        s, own_img, d.channels, d.height, d.width);
     img = own_img;

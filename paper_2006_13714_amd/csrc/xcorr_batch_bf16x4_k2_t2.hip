@@ -1,4 +1,4 @@
-// Persistent uneven-batch kernels: precision form bf16x3, K <= 32, 2 tile columns.
+// Persistent uneven-batch kernels: precision form bf16x4, K <= 32, 2 tile columns.
 #include "xcorr_batch.h"
 
 namespace bmk {

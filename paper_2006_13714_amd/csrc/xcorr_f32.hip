@@ -393,6 +393,7 @@ hipError_t launch_xcorr_f32(int ks_bucket, int kr, const float* img, const float
                             hipStream_t stream) {
   XcKernel k = f32_kernel(ks_bucket, kr);
   if (!k) return hipErrorInvalidValue;
+  (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
   hipLaunchKernelGGL(k, dim3(g.nwg_total), dim3(64 * g.WY * g.WX), g.lds_bytes, stream, img, nrm,
                      centers, idx, dist, g);
   return hipGetLastError();

@@ -102,7 +102,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
   constexpr int CRS = CT::CRS;
   constexpr int NB = CT::NB;
   using BReg = typename CT::BReg;
-  constexpr int NA = std::is_same_v<typename CT::AReg, float> ? CT::NS : 2 * (CT::NS / 3);
+  constexpr int NA = CT::NA;
   constexpr int TL = RefSelect<KR>::TL;
   static_assert(NT >= 1 && NT <= 4, "tile columns");
   constexpr int NW = kTileN * NT;  // norm strip row length

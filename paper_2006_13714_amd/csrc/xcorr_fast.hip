@@ -45,6 +45,7 @@ hipError_t launch_xcorr_fast(int prec, int c, int h2, int kr, int nt, const floa
                              int* idx, float* dist, const XcGeom& g, hipStream_t stream) {
   XcFastKernel k = fast_kernel(prec, c, h2, kr, nt);
   if (!k) return hipErrorInvalidValue;
+  (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
   hipLaunchKernelGGL(k, dim3(g.nwg_total), dim3(64 * g.WS), g.lds_bytes, stream, img, nrm,
                      centers, amax, idx, dist, fast_geom(g));
   return hipGetLastError();
@@ -75,6 +76,7 @@ hipError_t launch_xcorr_depth(int prec, int c, int h2, int kr, int nt, const flo
   if (!k) return hipErrorInvalidValue;
   const long long blocks = (long long)g.nwg_total * dg.Z;
   if (blocks < 1 || blocks >= (1ll << 31)) return hipErrorInvalidValue;
+  (void)hipGetLastError();  // a stale status (e.g. a query's not-ready) must not read as a launch failure
   hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * g.WS), g.lds_bytes, stream, vol, nrm,
                      amax, idx, dist, fast_geom(g), dg);
   return hipGetLastError();

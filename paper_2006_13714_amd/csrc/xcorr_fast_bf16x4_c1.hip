@@ -1,4 +1,4 @@
-// Specialised cross-term / top-K kernels: precision form bf16x3, 1 channel.
+// Specialised cross-term / top-K kernels: precision form bf16x4, 1 channel.
 #include "xcorr_fast.h"
 
 namespace bmk {

@@ -1,4 +1,4 @@
-// Specialised cross-term / top-K kernels: precision form bf16x3, 2 channels.
+// Specialised cross-term / top-K kernels: precision form bf16x4, 2 channels.
 #include "xcorr_fast.h"
 
 namespace bmk {

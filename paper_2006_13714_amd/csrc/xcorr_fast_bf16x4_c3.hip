@@ -1,4 +1,4 @@
-// Specialised cross-term / top-K kernels: precision form bf16x3, 3 channels.
+// Specialised cross-term / top-K kernels: precision form bf16x4, 3 channels.
 #include "xcorr_fast.h"
 
 namespace bmk {

@@ -1,4 +1,4 @@
-// Specialised cross-term / top-K kernels: precision form bf16x3, 4 channels.
+// Specialised cross-term / top-K kernels: precision form bf16x4, 4 channels.
 #include "xcorr_fast.h"
 
 namespace bmk {

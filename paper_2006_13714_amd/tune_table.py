@@ -21,14 +21,14 @@ import sys
 def slab_classes():
     """The one-slab 2D problems of the 3D search workloads (256 x 256 planes, 6 x 6 patches,
     stride 1, 31 x 31 windows, K = 16; 1-plane and 3-plane blocks): 3D plans look these up."""
-    return [(256, 256, C, 6, 1, 31, 16, prec) for prec in ("fp32", "bf16x3", "fp16x3")
+    return [(256, 256, C, 6, 1, 31, 16, prec) for prec in ("fp32", "bf16x4", "fp16x3")
             for C in (1, 3)]
 
 
 def classes():
     sides = (128, 512, 1024)  # one per reference-grid size bucket
     out = []
-    for prec in ("fp32", "bf16x3", "fp16x3"):
+    for prec in ("fp32", "bf16x4", "fp16x3"):
         for C in (1, 2, 3, 4):
             for P in ((6, 8) if C in (1, 3) else (8,)):
                 for H in sides:

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <set>
+#include <string>
 #include <vector>
 
 #include "serve_core.h"
@@ -68,6 +69,7 @@ class MockExecutor : public Executor {
   void wait_step(Step* s) override {
     while (!step_done(s)) std::this_thread::sleep_for(std::chrono::microseconds(50));
   }
+  std::string last_message() override { return "mock launch failure"; }
   std::atomic<bool> fail_next_{false};
   int64_t max_step_ = 0;
 
@@ -201,6 +203,63 @@ static void test_admission_by_footprint() {
   s.shutdown();
 }
 
+static void test_header_does_not_block_head() {
+  // The budget holds one request plus the header of a one-request step, but not the header
+  // sized for the six queued requests: every request must still run (one step each).
+  MockExecutor ex(64 << 20, 1e-7);
+  bm_desc d = desc(200, 200);
+  const int64_t need = (ex.request_bytes(d) + 255) / 256 * 256;
+  const int64_t h1 = (ex.step_header_bytes(1) + 255) / 256 * 256;
+  CHECK((ex.step_header_bytes(6) + 255) / 256 * 256 > h1);
+  bm_server_cfg cfg{need + h1, 64, 1024};
+  Scheduler s(&ex, cfg, cfg.hbm_budget_bytes, 64 << 20);
+  CHECK(s.start() == BM_OK);
+  std::vector<uint64_t> t;
+  std::vector<float> first;
+  for (int i = 0; i < 6; ++i) {
+    auto img = image(d, 3.f + i);
+    uint64_t tk;
+    const char* why = "";
+    CHECK(s.submit(d, img.data(), &tk, &why) == BM_OK);
+    t.push_back(tk);
+    first.push_back(3.f + i);
+  }
+  Request meta;
+  meta.desc = d;
+  meta.n_ref = desc_n_ref(d);
+  for (int i = 0; i < 6; ++i) {
+    std::vector<int32_t> idx(meta.n_ref * d.k);
+    std::vector<float> dist(meta.n_ref * d.k);
+    CHECK(wait_poll(s, t[i], &idx, &dist, nullptr) == BM_OK);
+    check_result(meta, t[i], first[i], idx, dist);
+  }
+  CHECK(ex.max_step_ == 1);
+  s.shutdown();
+}
+
+static void test_failure_message() {
+  // a failed step reports the executor's message with the status
+  MockExecutor ex(16 << 20, 1e-7);
+  bm_server_cfg cfg{64 << 20, 64, 1024};
+  Scheduler s(&ex, cfg, cfg.hbm_budget_bytes, 16 << 20);
+  CHECK(s.start() == BM_OK);
+  bm_desc d = desc(64, 64);
+  auto img = image(d, 1.f);
+  ex.fail_next_ = true;
+  uint64_t tk;
+  const char* why = "";
+  CHECK(s.submit(d, img.data(), &tk, &why) == BM_OK);
+  bm_status r;
+  std::string msg;
+  for (int i = 0; i < 200000; ++i) {
+    if ((r = s.poll(tk, nullptr, nullptr, nullptr, &msg)) != BM_EAGAIN) break;
+    std::this_thread::sleep_for(std::chrono::microseconds(50));
+  }
+  CHECK(r == BM_EDEVICE);
+  CHECK(msg == "mock launch failure");
+  s.shutdown();
+}
+
 static void test_continuous_batching_overlap() {
   // slow steps: requests that arrive while the first step runs are launched as further
   // steps before it completes
@@ -221,6 +280,28 @@ static void test_continuous_batching_overlap() {
   for (uint64_t tk : t) CHECK(wait_poll(s, tk, nullptr, nullptr, nullptr) == BM_OK);
   CHECK(s.steps_launched() >= 2);
   CHECK(s.max_overlap() >= 2);
+  s.shutdown();
+}
+
+static void test_max_step() {
+  // a step takes at most max_step requests even when many wait
+  MockExecutor ex(256 << 20, 1e-7);
+  bm_server_cfg cfg{512 << 20, 64, 1024, 3};
+  Scheduler s(&ex, cfg, cfg.hbm_budget_bytes, 256 << 20);
+  CHECK(s.start() == BM_OK);
+  std::vector<uint64_t> t;
+  for (int i = 0; i < 12; ++i) {
+    bm_desc d = desc(128, 128);
+    auto img = image(d, (float)i);
+    uint64_t tk;
+    const char* why;
+    CHECK(s.submit(d, img.data(), &tk, &why) == BM_OK);
+    t.push_back(tk);
+  }
+  for (uint64_t tk : t) CHECK(wait_poll(s, tk, nullptr, nullptr, nullptr) == BM_OK);
+  CHECK(ex.max_step_ <= 3);
+  CHECK(s.max_step_size() <= 3);
+  CHECK(s.steps_launched() >= 4);
   s.shutdown();
 }
 
@@ -339,6 +420,9 @@ int main() {
   test_alloc();
   test_basic_and_results();
   test_admission_by_footprint();
+  test_header_does_not_block_head();
+  test_max_step();
+  test_failure_message();
   test_continuous_batching_overlap();
   test_max_inflight_one();
   test_cancel_fail_and_limits();

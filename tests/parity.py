@@ -131,9 +131,12 @@ def check_exact(gpu_idx, gpu_dist, oidx, odist):
 
 # NCC tolerance on e = 2 - 2 NCC (absolute): float32 accumulation of n = P*P*C products
 # errs by at most n*u*||X_i||*||X_j|| (Cauchy-Schwarz), the reciprocal norms by a few u
-# each, so |de| <= 2 (n + 8) u ~ 3.1e-5 at n = 256; the split forms add their split
-# residual (float16: ~2^-22 relative, bfloat16 without lo*lo: ~2^-16 per product).
-NCC_TOL = {"fp32": 4e-5, "fp16x3": 4e-5, "bf16x3": 2e-4}
+# each, so |de| <= 2 (n + 8) u ~ 3.1e-5 at n = 256; the float16 split adds its ~2^-22
+# residual.  The bfloat16 split computes the NCC of the patches rounded to 16 significant
+# bits exactly (all four products, norms of the rounded values): rounding moves each
+# unit-normalised patch by at most 2^-15, so e = ||u_i - u_j||^2 <= 4 moves by at most
+# 2 * 2 * 2 * 2^-15 ~ 1.2e-4, and 2e-4 covers that plus the float32 part.
+NCC_TOL = {"fp32": 4e-5, "fp16x3": 4e-5, "bf16x4": 2e-4}
 
 
 def check_ncc(x, P, s, Wn, K, gpu_idx, gpu_dist, refs=None, tol=4e-5, report=None):
@@ -183,3 +186,97 @@ def check_ncc(x, P, s, Wn, K, gpu_idx, gpu_dist, refs=None, tol=4e-5, report=Non
                 rep.tolerant_mismatch += 1
                 rep.messages.append(f"ref {i}: set rule violated")
     return rep
+
+
+# ---------------------------------------------------------------------------------------
+# Whole-image parity from a cached oracle table.  The oracle's sorted head of every
+# reference (its K + EXTRA smallest (d*, j) under the (d, j) key, the candidate count, the
+# reference norm and the norms of the head's candidates) holds everything the distance
+# and set rules look at: the set rule's forced members (d* < t - tau) are oracle top-K
+# entries, and a GPU member outside the head has d* >= the head's last distance, so it
+# breaks the rule unless the head's last distance is itself within t + tau (then that
+# reference is checked against its full window instead).
+EXTRA = 16
+
+
+def _head_rows(args):
+    x64, P, Wn, K, pos = args
+    out = []
+    for ry, rx in pos:
+        d, j = O.window_distances(x64, P, Wn, int(ry), int(rx))
+        hj, hd = O.select_k(d, j, K + EXTRA)
+        out.append((d.size, hj, hd))
+    return out
+
+
+class OracleHead:
+    """Oracle heads of a set of references of one image (computed once, reused by every
+    form compared against it)."""
+
+    def __init__(self, x, P, s, Wn, K, refs=None):
+        x64 = np.asarray(x, dtype=np.float64)
+        if x64.ndim == 2:
+            x64 = x64[None]
+        self.x64, self.P, self.s, self.Wn, self.K = x64, P, s, Wn, K
+        C, H, W = x64.shape
+        self.N = O.patch_norms(x64, P)
+        self.rl = O.ref_list(H, W, P, s)
+        self.refs = np.arange(len(self.rl)) if refs is None else np.asarray(refs)
+        pos = self.rl[self.refs]
+        parts = [_head_rows((x64, P, Wn, K, pos))]
+        rows = [r for p in parts for r in p]
+        self.ncand = np.array([r[0] for r in rows])
+        self.hj = np.stack([r[1] for r in rows])
+        self.hd = np.stack([r[2] for r in rows])
+        self.ni = self.N[pos[:, 0], pos[:, 1]]
+        jj = np.maximum(self.hj, 0)
+        self.hn = np.where(self.hj >= 0, self.N[jj // W, jj % W], 0.0)
+
+    def check(self, gpu_idx, gpu_dist, tol=1e-4, floor=1e-2, report=None):
+        """Rows of the GPU result for self.refs (gpu_idx[self.refs] etc. already taken)."""
+        K = self.K
+        rep = report or ParityReport()
+        W = self.x64.shape[2]
+        for row, i in enumerate(self.refs):
+            gi, gd = np.asarray(gpu_idx[row]), np.asarray(gpu_dist[row])
+            kk = min(K, int(self.ncand[row]))
+            hj, hd, hn = self.hj[row], self.hd[row], self.hn[row]
+            t = hd[kk - 1]
+            tau = tol * max(t, floor * (self.ni[row] + hn[kk - 1]))
+            head_ok = kk < K or not (hd[-1] <= t + tau)  # the head covers every d* <= t + tau
+            members = gi[:kk].tolist()
+            pos = {int(j): q for q, j in enumerate(hj.tolist()) if j >= 0}
+            if not head_ok or any(m not in pos for m in members):
+                # outside the head (or a head too short for the band): full window
+                ry, rx = self.rl[i]
+                d, j = O.window_distances(self.x64, self.P, self.Wn, int(ry), int(rx))
+                N = self.N
+                _check_row(rep, i, d, j, K, gi, gd, self.ni[row],
+                           lambda m: N[m // W, m % W], tol, floor)
+                continue
+            rep.n_refs += 1
+            if np.any(gi[kk:] != -1) or np.any(np.isfinite(gd[kk:])):
+                rep.tolerant_mismatch += 1
+                rep.messages.append(f"ref {i}: bad padding")
+                continue
+            if len(set(members)) != kk:
+                rep.tolerant_mismatch += 1
+                rep.messages.append(f"ref {i}: duplicate indices {members}")
+                continue
+            q = np.array([pos[m] for m in members])
+            dstar = hd[q]
+            rel = np.abs(gd[:kk].astype(np.float64) - dstar) / np.maximum(dstar, floor * (self.ni[row] + hn[q]))
+            rep.rel.append(rel)
+            if np.any(rel > tol):
+                rep.tolerant_mismatch += 1
+                rep.messages.append(f"ref {i}: rel error {rel.max():.3e}")
+            keys = list(zip(gd[:kk].tolist(), members))
+            if keys != sorted(keys):
+                rep.order_violations += 1
+            if set(members) != set(hj[:kk].tolist()):
+                rep.strict_mismatch += 1
+                must = {int(a) for a, b in zip(hj[:kk], hd[:kk]) if b < t - tau}
+                if np.any(dstar > t + tau) or not must.issubset(set(members)):
+                    rep.tolerant_mismatch += 1
+                    rep.messages.append(f"ref {i}: set rule violated")
+        return rep

@@ -7,20 +7,25 @@ import pytest
 
 from tests.libutil import ROOT, ensure_built
 
-HEADER = os.path.join(ROOT, "include", "bm.h")
+INCLUDE = os.path.join(ROOT, "include")
 
 
 def declared_functions():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(bm_[a-z_]+)\s*\(", txt)))
+    """Every bm_* function declared in include/*.h (comments stripped)."""
+    names = set()
+    for f in sorted(os.listdir(INCLUDE)):
+        if f.endswith(".h"):
+            txt = re.sub(r"/\*.*?\*/", "", open(os.path.join(INCLUDE, f)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(bm_[a-z_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ["bm_plan", "bm_plan_info", "bm_match", "bm_match_batch", "bm_plan_destroy",
               "bm_server_create", "bm_submit", "bm_poll", "bm_cancel", "bm_server_destroy",
-              "bm_status_str", "bm_last_error", "bm_norms", "bm_batch_workspace"]:
+              "bm_status_str", "bm_last_error", "bm_norms", "bm_batch_workspace",
+              "bm_peak_mfma", "bm_peak_copy"]:
         assert n in names
 
 

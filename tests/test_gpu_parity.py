@@ -76,6 +76,30 @@ def test_norm_map(gpu):
     assert np.max(np.abs(got - ref) / ref) <= 2 ** -23
 
 
+def test_norm_map_bf16_rounded(gpu):
+    """A bfloat16 split plan's norm map holds the norms of the image rounded to hi + lo
+    (hi = bf16(x), lo = bf16(x - hi), round to nearest even; rounded here with torch's own
+    conversion on the CPU), each the float32 rounding of the exact sum."""
+    import torch
+    banner("norm map bf16x4 rounded 2ch 61x77 P=8")
+    bm = ensure_built()
+    x = synth.random_image(4, 2, 61, 77, -1.0, 3.0)
+    plan = bm.bm_plan(bm.make_desc(61, 77, 2, 8, 3, 21, 16, "bf16x4"))
+    t = torch.from_numpy(x).cuda()
+    out = torch.empty((54, 70), dtype=torch.float32, device="cuda")
+    bm.bm_norms(plan, t, out)
+    torch.cuda.synchronize()
+    xt = torch.from_numpy(x)
+    hi = xt.to(torch.bfloat16).to(torch.float32)
+    lo = (xt - hi).to(torch.bfloat16).to(torch.float32)
+    xr = (hi.double() + lo.double()).numpy()
+    ref = O.patch_norms(xr, 8)
+    got = out.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - ref) / ref) <= 2 ** -23
+    # and they differ from the unrounded norms by the rounding (relative ~2^-16 or less)
+    assert np.max(np.abs(got - O.patch_norms(x, 8)) / ref) < 2 ** -14
+
+
 def test_small_gray_smooth_full(gpu):
     w = synth.small_gray()
     sh = w.shape
@@ -137,3 +161,32 @@ def test_deterministic(gpu):
     a = run(w.image, sh.patch, sh.stride, sh.window, sh.k)
     b = run(w.image, sh.patch, sh.stride, sh.window, sh.k)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1].view(np.int32), b[1].view(np.int32))
+
+
+def test_cached_plan_on_two_streams(gpu):
+    """bm.match on one cached plan from two streams at once: each call has its own
+    workspace (norm map, max map), so both results equal the same calls made one at a
+    time."""
+    import torch
+    banner("cached plan, two streams")
+    bm = ensure_built()
+    xs = [synth.gray_voronoi(s, 200, 180) for s in (41, 42)]
+    ts = [torch.from_numpy(x).cuda() for x in xs]
+    want = []
+    for t in ts:
+        i, d = bm.match(t, 8, 3, 21, 16, "fp16x3")
+        torch.cuda.synchronize()
+        want.append((i.cpu().numpy(), d.cpu().numpy()))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    got = []
+    for rep in range(4):
+        outs = []
+        for t, s in zip(ts, streams):
+            with torch.cuda.stream(s):
+                outs.append(bm.match(t, 8, 3, 21, 16, "fp16x3", stream=s))
+        torch.cuda.synchronize()
+        got.append([(i.cpu().numpy(), d.cpu().numpy()) for i, d in outs])
+    for g in got:
+        for (gi, gd), (wi, wd) in zip(g, want):
+            assert np.array_equal(gi, wi) and np.array_equal(gd.view(np.int32), wd.view(np.int32))

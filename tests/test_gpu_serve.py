@@ -37,7 +37,7 @@ def wait(bm, srv, ticket, n_ref, k, timeout=60.0):
         time.sleep(0.0005)
 
 
-def requests(seed, n, max_side=384, precisions=("bf16x3", "fp16x3", "fp32")):
+def requests(seed, n, max_side=384, precisions=("bf16x4", "fp16x3", "fp32")):
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
@@ -75,7 +75,7 @@ def test_serving_mix_equals_single_and_oracle(gpu):
             assert np.array_equal(dist.view(np.uint32), sdist.view(np.uint32)), (x.shape, prec)
             assert stats.n_ref == n_ref and stats.total_s >= stats.device_s >= 0
             refs = np.sort(rng.choice(n_ref, size=min(8, n_ref), replace=False))
-            tol = 2e-3 if prec == "bf16x3" else 1e-4
+            tol = 1e-4
             rep = parity.check(x, d.patch, d.stride, d.window, d.k, idx[refs], dist[refs],
                                refs=refs, tol=tol)
             assert rep.tolerant_mismatch == 0 and rep.order_violations == 0, rep.summary()
@@ -87,7 +87,7 @@ def test_serving_alone_equals_in_mix(gpu):
     banner("serving: one request alone and inside a mix")
     bm = ensure_built()
     x = synth.multichannel_voronoi(77, 300, 260, 3, 50.0)
-    d = desc_for(bm, x, "bf16x3")
+    d = desc_for(bm, x, "bf16x4")
     n_ref = bm.cached_plan(d).n_ref
     srv = bm.bm_server_create(1 << 30, max_inflight=16, max_queue=256)
     try:
@@ -156,7 +156,7 @@ def test_serving_cancel_and_errors(gpu):
             bm.bm_poll(srv, t1)  # retired
         assert ei.value.status == bm.BM_ENOTFOUND
         with pytest.raises(bm.BMError) as ei:  # split form outside its envelope
-            bm.bm_submit(srv, bm.make_desc(64, 64, 1, 10, 3, 39, 16, "bf16x3"), np.zeros((1, 64, 64), np.float32))
+            bm.bm_submit(srv, bm.make_desc(64, 64, 1, 10, 3, 39, 16, "bf16x4"), np.zeros((1, 64, 64), np.float32))
         assert ei.value.status == bm.BM_ENOTSUP
     finally:
         bm.bm_server_destroy(srv)
