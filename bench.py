@@ -459,9 +459,11 @@ def main():
         for f, (pf, wf, nf, xf, sf, _) in ncc.items()}
     out["volumes"] = volumes(bm, synth, torch, max(3, args.steps // 20), 2)
     # measured attainable peaks beside the published ones
-    peaks = {f: bm.bm_peak_mfma(f) for f in PEAK_TFLOPS}
+    peaks = {f: bm.bm_peak_mfma(f, 0) for f in PEAK_TFLOPS}
+    peaks32 = {f: bm.bm_peak_mfma(f, 1) for f in PEAK_TFLOPS}
     copy_gbps = bm.bm_peak_copy(1 << 30, 5)
-    out["peaks_measured"] = {"mfma_tflops": peaks, "copy_GBps": copy_gbps,
+    out["peaks_measured"] = {"mfma_tflops": peaks, "mfma_32x32_tflops": peaks32,
+                             "copy_GBps": copy_gbps,
                              "published": {"mfma_tflops": PEAK_TFLOPS, "hbm_GBps": 8000.0}}
     out["roofline"]["peak_measured"] = peaks[prec]
     out["roofline"]["frac_measured"] = achieved / peaks[prec]

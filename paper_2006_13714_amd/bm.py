@@ -85,7 +85,7 @@ _SIGS = {
     "bm_server_destroy": (C.c_int32, [C.c_void_p]),
     "bm_autotune": (C.c_int32, [C.POINTER(bm_desc), C.c_void_p, C.c_int32, C.c_char_p, C.c_int32]),
     "bm_plan_config": (C.c_int32, [C.c_void_p, C.c_char_p, C.c_int32, C.POINTER(C.c_int32)]),
-    "bm_peak_mfma": (C.c_int32, [C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
+    "bm_peak_mfma": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
     "bm_peak_copy": (C.c_int32, [C.c_int64, C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
     "bm_status_str": (C.c_char_p, [C.c_int32]),
     "bm_last_error": (C.c_char_p, []),
@@ -256,11 +256,13 @@ def bm_plan_config(plan: Plan):
     return out.value.decode(), src.value
 
 
-def bm_peak_mfma(precision, iterations: int = 20000, stream=None) -> float:
-    """Measured matrix-core rate (TFLOP/s) of the instruction a precision form issues."""
+def bm_peak_mfma(precision, shape: int = 0, iterations: int = 20000, stream=None) -> float:
+    """Measured matrix-core rate (TFLOP/s) of a precision form's 16x16 (shape 0, the one the
+    kernels issue) or 32x32 (shape 1) matrix instruction."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     out = C.c_double()
-    _check(lib().bm_peak_mfma(prec, iterations, _stream(stream), C.byref(out)), "bm_peak_mfma")
+    _check(lib().bm_peak_mfma(prec, shape, iterations, _stream(stream), C.byref(out)),
+           "bm_peak_mfma")
     return out.value
 
 

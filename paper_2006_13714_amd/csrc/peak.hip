@@ -7,6 +7,8 @@
 
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/bm.h"
 #include "../../include/bm_peak.h"
 #include "plan.h"
@@ -20,11 +22,16 @@ typedef _Float16 h8p __attribute__((ext_vector_type(8)));
 
 constexpr int kPeakChains = 4;
 
-template <int PREC>
+typedef float f16p __attribute__((ext_vector_type(16)));
+
+// SHAPE 0: the 16 x 16 instructions the cross-term kernels issue; SHAPE 1: the 32 x 32
+// instructions of the same precision (for comparison of the two shapes' rates).
+template <int PREC, int SHAPE>
 __global__ void __launch_bounds__(256) mfma_loop_kernel(float* out, int iters, float seed) {
-  f4p acc[kPeakChains];
+  using Acc = std::conditional_t<SHAPE == 0, f4p, f16p>;
+  Acc acc[kPeakChains];
 #pragma unroll
-  for (int q = 0; q < kPeakChains; ++q) acc[q] = f4p{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < kPeakChains; ++q) acc[q] = Acc{};
   const float a = seed * (float)(threadIdx.x + 1), b = seed * 0.5f;
   u4p ua, ub;
 #pragma unroll
@@ -35,27 +42,48 @@ __global__ void __launch_bounds__(256) mfma_loop_kernel(float* out, int iters, f
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
     for (int q = 0; q < kPeakChains; ++q) {
-      if constexpr (PREC == BM_PREC_FP32)
-        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
-      else if constexpr (PREC == BM_PREC_FP16X3)
-        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8p, ua),
-                                                        __builtin_bit_cast(h8p, ub), acc[q], 0, 0, 0);
-      else
-        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8p, ua),
-                                                         __builtin_bit_cast(bf8p, ub), acc[q], 0, 0, 0);
+      if constexpr (SHAPE == 0) {
+        if constexpr (PREC == BM_PREC_FP32)
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
+        else if constexpr (PREC == BM_PREC_FP16X3)
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8p, ua),
+                                                          __builtin_bit_cast(h8p, ub), acc[q], 0, 0, 0);
+        else
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8p, ua),
+                                                           __builtin_bit_cast(bf8p, ub), acc[q], 0, 0, 0);
+      } else {
+        if constexpr (PREC == BM_PREC_FP32)
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[q], 0, 0, 0);
+        else if constexpr (PREC == BM_PREC_FP16X3)
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8p, ua),
+                                                          __builtin_bit_cast(h8p, ub), acc[q], 0, 0, 0);
+        else
+          acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8p, ua),
+                                                           __builtin_bit_cast(bf8p, ub), acc[q], 0, 0, 0);
+      }
     }
   }
   float s = 0.f;
 #pragma unroll
-  for (int q = 0; q < kPeakChains; ++q) s += acc[q][0] + acc[q][1] + acc[q][2] + acc[q][3];
+  for (int q = 0; q < kPeakChains; ++q)
+#pragma unroll
+    for (int i = 0; i < (SHAPE == 0 ? 4 : 16); ++i) s += acc[q][i];
   if (s == 1234.5f) out[threadIdx.x] = s;  // keeps the chains live; never true in practice
 }
 
+// Grid-stride copy, four float4 loads in flight per thread before their stores.
 __global__ void __launch_bounds__(256) copy_kernel(const f4p* __restrict__ src,
                                                    f4p* __restrict__ dst, int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-    dst[i] = src[i];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const f4p v0 = src[i], v1 = src[i + stride], v2 = src[i + 2 * stride], v3 = src[i + 3 * stride];
+    dst[i] = v0;
+    dst[i + stride] = v1;
+    dst[i + 2 * stride] = v2;
+    dst[i + 3 * stride] = v3;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
 }
 
 }  // namespace bmk
@@ -64,8 +92,9 @@ using namespace bmk;
 
 extern "C" {
 
-bm_status bm_peak_mfma(int32_t precision, int32_t iterations, void* stream, double* tflops) {
-  if (!tflops || iterations < 1) return fail(BM_EINVAL, "bad argument");
+bm_status bm_peak_mfma(int32_t precision, int32_t shape, int32_t iterations, void* stream,
+                       double* tflops) {
+  if (!tflops || iterations < 1 || shape < 0 || shape > 1) return fail(BM_EINVAL, "bad argument");
   if (precision < BM_PREC_FP32 || precision > BM_PREC_FP16X3)
     return fail(BM_EINVAL, "unknown precision %d", precision);
   int dev = 0, n_cu = 0;
@@ -75,19 +104,29 @@ bm_status bm_peak_mfma(int32_t precision, int32_t iterations, void* stream, doub
   hipStream_t s = (hipStream_t)stream;
   float* out = nullptr;
   if ((e = hipMalloc(&out, 256 * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc");
-  // two 4-wave blocks per compute unit: two waves per SIMD
-  const int blocks = 2 * n_cu;
+  // four 4-wave blocks per compute unit: four waves per SIMD
+  const int blocks = 4 * n_cu;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   (void)hipEventCreate(&t0);
   (void)hipEventCreate(&t1);
   auto launch = [&](int iters) {
     (void)hipGetLastError();
-    if (precision == BM_PREC_FP32)
-      hipLaunchKernelGGL(mfma_loop_kernel<BM_PREC_FP32>, dim3(blocks), dim3(256), 0, s, out, iters, 1e-3f);
-    else if (precision == BM_PREC_FP16X3)
-      hipLaunchKernelGGL(mfma_loop_kernel<BM_PREC_FP16X3>, dim3(blocks), dim3(256), 0, s, out, iters, 1e-3f);
-    else
-      hipLaunchKernelGGL(mfma_loop_kernel<BM_PREC_BF16X4>, dim3(blocks), dim3(256), 0, s, out, iters, 1e-3f);
+    const dim3 g(blocks), b(256);
+    if (shape == 0) {
+      if (precision == BM_PREC_FP32)
+        hipLaunchKernelGGL((mfma_loop_kernel<BM_PREC_FP32, 0>), g, b, 0, s, out, iters, 1e-3f);
+      else if (precision == BM_PREC_FP16X3)
+        hipLaunchKernelGGL((mfma_loop_kernel<BM_PREC_FP16X3, 0>), g, b, 0, s, out, iters, 1e-3f);
+      else
+        hipLaunchKernelGGL((mfma_loop_kernel<BM_PREC_BF16X4, 0>), g, b, 0, s, out, iters, 1e-3f);
+    } else {
+      if (precision == BM_PREC_FP32)
+        hipLaunchKernelGGL((mfma_loop_kernel<BM_PREC_FP32, 1>), g, b, 0, s, out, iters, 1e-3f);
+      else if (precision == BM_PREC_FP16X3)
+        hipLaunchKernelGGL((mfma_loop_kernel<BM_PREC_FP16X3, 1>), g, b, 0, s, out, iters, 1e-3f);
+      else
+        hipLaunchKernelGGL((mfma_loop_kernel<BM_PREC_BF16X4, 1>), g, b, 0, s, out, iters, 1e-3f);
+    }
     return hipGetLastError();
   };
   e = launch(iterations / 8 + 1);  // warm-up (clocks)
@@ -101,9 +140,10 @@ bm_status bm_peak_mfma(int32_t precision, int32_t iterations, void* stream, doub
   (void)hipEventDestroy(t1);
   (void)hipFree(out);
   if (e != hipSuccess) return hip_fail(e, "matrix-op probe");
-  const double per_op = precision == BM_PREC_FP32 ? 2.0 * 16 * 16 * 4 : 2.0 * 16 * 16 * 32;
+  const double mn = shape == 0 ? 16.0 * 16 : 32.0 * 32;
+  const double k = precision == BM_PREC_FP32 ? (shape == 0 ? 4 : 2) : (shape == 0 ? 32 : 16);
   const double ops = (double)blocks * 4 /*waves*/ * kPeakChains * (double)iterations;
-  *tflops = per_op * ops / (ms * 1e-3) / 1e12;
+  *tflops = 2.0 * mn * k * ops / (ms * 1e-3) / 1e12;
   return BM_OK;
 }
 
@@ -124,7 +164,7 @@ bm_status bm_peak_copy(int64_t bytes, int32_t repeats, void* stream, double* gbp
   hipEvent_t t0 = nullptr, t1 = nullptr;
   (void)hipEventCreate(&t0);
   (void)hipEventCreate(&t1);
-  const int blocks = 8 * n_cu;
+  const int blocks = 16 * n_cu;
   float best = 0.f;
   e = hipMemsetAsync(src, 0, n * 16, s);
   for (int r = 0; r <= repeats && e == hipSuccess; ++r) {  // r = 0: warm-up
