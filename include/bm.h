@@ -122,6 +122,20 @@ bm_status bm_plan_info(bm_plan_t plan, int64_t* n_ref, int64_t* workspace_bytes)
 bm_status bm_match(bm_plan_t plan, const float* d_img, int32_t* d_idx, float* d_dist,
                    void* d_workspace, void* stream);
 
+/* bm_match for callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the same kernels and results as
+ * bm_match, with the workspace in a fixed device array of BM_NOALLOC_MAX_WORKSPACE bytes
+ * that the library holds on each device it runs on until the process ends.  The call
+ * allocates nothing (no hipMalloc, no host allocation on the call path after the first
+ * call on a device, which looks up the array's address).  The plan must have been made on
+ * the current device.  BM_EINVAL if the plan's workspace_bytes exceed the maximum (the
+ * message names both sizes) or on NULL pointers.  Every call on a device shares that
+ * device's array, so calls that overlap in time on one device (other streams, other
+ * threads) race; the caller serialises them.  Asynchronous on `stream`. */
+#define BM_NOALLOC_MAX_WORKSPACE (32ll << 20)
+bm_status bm_match_noalloc(bm_plan_t plan, const float* d_img, int32_t* d_idx, float* d_dist,
+                           void* stream);
+
 /* Patch-norm map alone (the box filter, h_X (.) h_X of Sec. III-B): d_norm receives
  * (H-P+1)*(W-P+1) floats, row-major (3D plans: one such map per slab z = 0..q-d, stacked by
  * z, each the norms of the d-plane blocks at that depth).  BM_PREC_BF16X4 plans: the norms

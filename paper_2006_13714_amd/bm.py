@@ -63,6 +63,7 @@ _SIGS = {
     "bm_plan": (C.c_int32, [C.POINTER(bm_desc), C.POINTER(C.c_void_p)]),
     "bm_plan_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "bm_match": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bm_match_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bm_norms": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "bm_cross_topk": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p]),
@@ -191,6 +192,11 @@ def bm_plan_info(plan: Plan):
 def bm_match(plan: Plan, img, idx, dist, workspace=None, stream=None):
     _check(lib().bm_match(plan.handle, _ptr(img), _ptr(idx), _ptr(dist), _ptr(workspace),
                           _stream(stream)), "bm_match")
+
+
+def bm_match_noalloc(plan: Plan, img, idx, dist, stream=None):
+    _check(lib().bm_match_noalloc(plan.handle, _ptr(img), _ptr(idx), _ptr(dist),
+                                  _stream(stream)), "bm_match_noalloc")
 
 
 def bm_norms(plan: Plan, img, norm, stream=None):
