@@ -17,8 +17,10 @@ What it computes is the plain definition of block matching, written out slowly:
 
 Readings taken where the paper is silent (each one is listed in the design notes):
 
-* the window of side Wn (odd) holds the candidate top-left offsets (dy, dx) in
-  [-r, r]^2, r = (Wn - 1) / 2, so N_s = Wn^2 candidates away from borders;
+* the window of side Wn holds the candidate top-left offsets (dy, dx) in [-a, b]^2 with
+  a = floor(Wn / 2) and b = Wn - 1 - a: [-r, r]^2, r = (Wn - 1) / 2, for odd Wn, and
+  [-Wn/2, Wn/2 - 1]^2 for even Wn (the paper's 30 x 30), so N_s = Wn^2 candidates away
+  from borders;
 * at image borders the window is intersected with the valid positions, never shifted;
 * references sit on the grid {0, s, 2s, ...} in each axis (the last row/column is not
   forced in); candidates use stride 1 (all overlapping patches);
@@ -82,10 +84,18 @@ def ref_list(H: int, W: int, P: int, s: int):
     return np.stack([yy.ravel(), xx.ravel()], axis=1)
 
 
+def window_offsets(Wn: int):
+    """Smallest and largest candidate offset per axis of a window of side Wn: -floor(Wn/2)
+    and Wn - 1 - floor(Wn/2) (equal magnitudes for odd Wn; one fewer after than before the
+    reference for even Wn)."""
+    a = Wn // 2
+    return -a, Wn - 1 - a
+
+
 def window_box(ry: int, rx: int, Hv: int, Wv: int, Wn: int):
     """Inclusive candidate box of reference (ry, rx): the Wn x Wn offsets clipped to the image."""
-    r = Wn // 2
-    return max(0, ry - r), min(Hv - 1, ry + r), max(0, rx - r), min(Wv - 1, rx + r)
+    lo, hi = window_offsets(Wn)
+    return max(0, ry + lo), min(Hv - 1, ry + hi), max(0, rx + lo), min(Wv - 1, rx + hi)
 
 
 def candidate_count(H: int, W: int, P: int, s: int, Wn: int) -> int:

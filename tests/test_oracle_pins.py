@@ -51,11 +51,14 @@ def load_worked_example():
 
 
 def pure_python_bm(img, P, s, Wn, K):
-    """Independent brute force: nested Python loops over pixels, no numpy arithmetic."""
+    """Independent brute force: nested Python loops over pixels, no numpy arithmetic.  The
+    window is the list of offsets it holds: Wn of them per axis, as many before the
+    reference as after for odd Wn, one more before than after for even Wn."""
     C = len(img)
     H = len(img[0])
     W = len(img[0][0])
-    r = Wn // 2
+    offs = list(range(-(Wn // 2), Wn - Wn // 2))
+    assert len(offs) == Wn
     Hv, Wv = H - P + 1, W - P + 1
     out = []
     for ry in range(0, Hv, s):
@@ -63,7 +66,7 @@ def pure_python_bm(img, P, s, Wn, K):
             cands = []
             for qy in range(Hv):
                 for qx in range(Wv):
-                    if abs(qy - ry) > r or abs(qx - rx) > r:
+                    if (qy - ry) not in offs or (qx - rx) not in offs:
                         continue
                     acc = 0.0
                     for c in range(C):
@@ -100,6 +103,26 @@ def test_worked_example_norms_and_matches():
     assert N[ry, rx] + N[qy, qx] - 2 * cval == d
 
 
+def test_worked_example_even_window():
+    """Hand-derived even-window example (tests/golden/worked_even_window.txt)."""
+    with open(os.path.join(GOLDEN, "worked_even_window.txt")) as f:
+        lines = [ln.strip() for ln in f if ln.strip() and not ln.startswith("#")]
+    h, w = (int(v) for v in lines[0].split()[1:3])
+    img = np.array([[float(v) for v in lines[1 + y].split()] for y in range(h)])[None]
+    params = dict(kv.split("=") for kv in lines[1 + h].split()[1:])
+    P, s, Wn, K = (int(params[k]) for k in ("P", "s", "Wn", "K"))
+    rl = [tuple(r) for r in O.ref_list(h, w, P, s).tolist()]
+    idx, dist = O.bm(img, P, s, Wn, K)
+    for ln in lines[2 + h:]:
+        left, right = ln[4:].split(":")
+        ry, rx = (int(v) for v in left.split())
+        want_i = [int(v) for v in right.split("|")[0].split()]
+        want_d = [float(v) for v in right.split("|")[1].split()]
+        n = rl.index((ry, rx))
+        assert list(idx[n]) == want_i
+        assert list(dist[n]) == want_d
+
+
 # --------------------------------------------------------------------------------------
 # 2. brute force on tiny inputs (independent pure-Python implementation)
 # --------------------------------------------------------------------------------------
@@ -109,6 +132,8 @@ def test_worked_example_norms_and_matches():
     (2, 3, 10, 7, 4, 3, 7, 5),
     (3, 1, 6, 6, 6, 1, 1, 2),    # patch = image: one reference, one candidate
     (4, 1, 12, 9, 3, 4, 9, 40),
+    (5, 2, 9, 10, 3, 2, 4, 7),   # even windows (offsets -Wn/2 .. Wn/2 - 1)
+    (6, 1, 11, 8, 2, 3, 6, 30),
 ])
 def test_matches_pure_python_brute_force(seed, C, H, W, P, s, Wn, K):
     x = rng_img(seed, C, H, W)
@@ -302,15 +327,25 @@ def test_symmetry_between_references():
 # --------------------------------------------------------------------------------------
 # 6. counting identities
 # --------------------------------------------------------------------------------------
-def _axis_sum(nv, s, r):
-    return sum(min(nv - 1, c + r) - max(0, c - r) + 1 for c in range(0, nv, s))
+def _axis_sum(nv, s, r, r_after=None):
+    r_after = r if r_after is None else r_after
+    return sum(min(nv - 1, c + r_after) - max(0, c - r) + 1 for c in range(0, nv, s))
 
 
-@pytest.mark.parametrize("H,W,P,s,Wn", [(64, 64, 8, 3, 21), (40, 57, 6, 4, 13), (33, 20, 5, 1, 3)])
+@pytest.mark.parametrize("H,W,P,s,Wn", [(64, 64, 8, 3, 21), (40, 57, 6, 4, 13), (33, 20, 5, 1, 3),
+                                        (50, 41, 6, 1, 30), (37, 37, 4, 3, 8)])
 def test_candidate_count_separable(H, W, P, s, Wn):
-    r = Wn // 2
-    closed = _axis_sum(H - P + 1, s, r) * _axis_sum(W - P + 1, s, r)
+    before, after = Wn // 2, (Wn - 1) // 2
+    closed = _axis_sum(H - P + 1, s, before, after) * _axis_sum(W - P + 1, s, before, after)
     assert O.candidate_count(H, W, P, s, Wn) == closed
+
+
+def test_even_window_interior_count():
+    # away from borders an even window holds exactly Wn^2 candidates: 30 x 30 = 900
+    d, j = O.window_distances(np.zeros((1, 100, 100)), 6, 30, 40, 50)
+    assert d.size == 900
+    qy, qx = j // 100, j % 100
+    assert (qy.min(), qy.max(), qx.min(), qx.max()) == (25, 54, 35, 64)
 
 
 def test_gray512_pair_count():
@@ -373,3 +408,10 @@ def test_planted_tie_break_mistake_is_caught(monkeypatch):
     monkeypatch.setattr(O, "select_k", descending_ties)
     with pytest.raises(AssertionError):
         test_constant_image_ties_break_by_index()
+
+
+def test_planted_even_window_mistake_is_caught(monkeypatch):
+    """An even window placed one offset later (-(Wn/2 - 1) .. Wn/2) fails the hand pin."""
+    monkeypatch.setattr(O, "window_offsets", lambda Wn: (-((Wn - 1) // 2), Wn // 2))
+    with pytest.raises(AssertionError):
+        test_worked_example_even_window()
