@@ -18,7 +18,9 @@
  * References  top-left corners on the grid {0, s, 2s, ...} in each axis; n_ref =
  *             (floor((H-P)/s)+1) * (floor((W-P)/s)+1), numbered row-major.
  * Candidates  every valid patch position (stride 1) whose offset from the reference lies in
- *             [-r, r]^2, r = (window-1)/2, intersected with the image (never shifted).
+ *             [-a, b]^2 with a = floor(window/2), b = window - 1 - a (odd windows: [-r, r],
+ *             r = (window-1)/2; even windows one more offset before the reference than
+ *             after), intersected with the image (never shifted).
  *             The reference is its own candidate (distance 0).
  * Output      idx[i*K + k] = qy*W + qx (int32) and dist[i*K + k] (float32, clamped at 0),
  *             sorted ascending by the key (dist, idx); rows with fewer than K candidates
@@ -74,7 +76,7 @@ typedef int32_t bm_status;
                                dist reports 2 - 2 NCC in [0, 4] (the squared distance of the
                                unit-normalised patches), ascending; NCC is 0 when either
                                patch has zero norm.  Needs the specialised kernel (C <= 4,
-                               patch 3..8, K <= 32, 3*stride + window <= 48; BM_ENOTSUP
+                               patch 3..8, K <= 32, 17 <= 3*stride + window <= 48; BM_ENOTSUP
                                otherwise); not combinable with BM_FLAG_CENTER (BM_EINVAL). */
 
 /* One BM problem, following the paper's statement of BM: image, patch size sqrt(n),
@@ -89,13 +91,15 @@ typedef int32_t bm_status;
  * z..z+1) intersected with 0..q-d, never shifted, times the clipped 2D window.  Returned
  * indices are volume positions (z' * H + y) * W + x; order and padding as in 2D.  Needs the
  * specialised kernel's envelope for a d-channel image (d <= 4, patch 3..8 (5..8 split),
- * K <= 32, 3*stride + window <= 48), no flags (BM_ENOTSUP otherwise); q * H * W < 2^31.
+ * K <= 32, 17 <= 3*stride + window <= 48), no flags (BM_ENOTSUP otherwise); q * H * W < 2^31.
  * Both fields 0: the plain 2D problem. */
 typedef struct {
   int32_t height, width, channels; /* image H, W, C; 1 <= C <= 8 (3D: q <= 65536)       */
   int32_t patch;                   /* patch side P, 1 <= P <= 16, P <= min(H, W)        */
   int32_t stride;                  /* reference-grid stride s >= 1                      */
-  int32_t window;                  /* window side Wn, odd, >= 1                         */
+  int32_t window;                  /* window side Wn >= 1: candidate offsets -floor(Wn/2)
+                                      .. Wn - 1 - floor(Wn/2) per axis (odd Wn: -r..r;
+                                      even Wn, e.g. the paper's 30: -Wn/2 .. Wn/2 - 1)   */
   int32_t k;                       /* neighbours kept, 1 <= K <= 64                     */
   int32_t precision;               /* BM_PREC_*                                         */
   uint32_t flags;                  /* BM_FLAG_*                                         */

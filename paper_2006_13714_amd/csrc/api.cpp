@@ -51,7 +51,7 @@ bm_status validate_desc(const bm_desc* d) {
   if (d->patch > d->height || d->patch > d->width)
     return fail(BM_EINVAL, "patch %d larger than the image", d->patch);
   if (d->stride < 1) return fail(BM_EINVAL, "stride must be >= 1");
-  if (d->window < 1 || (d->window & 1) == 0) return fail(BM_EINVAL, "window must be odd and >= 1");
+  if (d->window < 1) return fail(BM_EINVAL, "window must be >= 1");
   if (d->k < 1 || d->k > kMaxK) return fail(BM_EINVAL, "k must be in [1, %d]", kMaxK);
   if (d->precision < BM_PREC_FP32 || d->precision > BM_PREC_FP16X3)
     return fail(BM_EINVAL, "unknown precision %d", d->precision);
@@ -82,7 +82,8 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g,
   g.P = d.patch;
   g.Pe = d.patch + (d.patch & 1);
   g.s = d.stride;
-  g.r = d.window / 2;
+  g.r = d.window / 2;  // even windows: one more offset before the reference than after
+  g.wspan = d.window - 1;
   g.K = d.k;
   g.Hv = d.height - d.patch + 1;
   g.Wv = d.width - d.patch + 1;
@@ -101,7 +102,7 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g,
   g.nwg_y = (g.nry + rows_per_wg - 1) / rows_per_wg;
   g.nwg_x = (g.nrx + cols_per_wg - 1) / cols_per_wg;
   g.nwg_total = g.nwg_y * g.nwg_x;
-  const int span = 3 * g.s + 2 * g.r + 1;  // candidate positions across a 4-reference block
+  const int span = 3 * g.s + g.wspan + 1;  // candidate positions across a 4-reference block
   g.NT = (span + kTileN - 1) / kTileN;
   g.NH = (fast ? 0 : 4 * g.s * (wy - 1)) + span;
   g.NW = (fast ? 0 : 4 * g.s * (wx - 1)) + kTileN * g.NT;
@@ -183,6 +184,7 @@ static GroupGeom group_geom(const bm_plan_s& p) {
   g.cnt_bits = bits;
   g.s = p.geom.s;
   g.r = p.geom.r;
+  g.wspan = p.geom.wspan;
   g.nry = p.geom.nry;
   g.nrx = p.geom.nrx;
   aggregate_tiling(g);
@@ -235,7 +237,7 @@ bm_status bm_plan(const bm_desc* desc, bm_plan_t* out) {
   if (st == BM_OK && plan_is_3d(*p)) {
     if (!p->geom.fast) {
       st = fail(BM_ENOTSUP, "3D search needs patch 3..8 (5..8 split), K <= 32 and "
-                            "3*stride + window <= 48");
+                            "17 <= 3*stride + window <= 48");
     } else {
       // the 3D kernel stages candidate norms in LDS with each slab's strip; the 2D
       // configuration was sized without that strip, so if it no longer fits, take the

@@ -27,7 +27,8 @@ constexpr int kNormTY = 8;
 
 // Geometry of one fused cross-term / distance / top-K launch.  All sizes in elements.
 struct XcGeom {
-  int H, W, C, P, Pe, s, r, K;
+  int H, W, C, P, Pe, s, r, K;  // r: candidate offsets before the reference (floor(Wn/2))
+  int wspan;            // Wn - 1: offsets run from -r to -r + wspan on each axis
   int Hv, Wv;           // valid patch positions per axis
   int nry, nrx;         // reference grid
   int WY, WX;           // wave grid inside a workgroup (each wave: 4 x 4 references)
@@ -60,6 +61,7 @@ struct DepthGeom {
 // single-image launch; per-image record of the batch launch).
 struct FastGeom {
   int H, W, Hv, Wv, P, s, r, K;
+  int wspan;  // window offsets -r .. -r + wspan
   int nry, nrx, nwg_x, nwg_total;
   int SH, SW, NH, CAP, p1_step;
   int lds_strip_off, lds_norm_off, lds_buf_off;
@@ -70,6 +72,7 @@ struct FastGeom {
 inline FastGeom fast_geom(const XcGeom& g) {
   FastGeom f;
   f.H = g.H; f.W = g.W; f.Hv = g.Hv; f.Wv = g.Wv; f.P = g.P; f.s = g.s; f.r = g.r; f.K = g.K;
+  f.wspan = g.wspan;
   f.nry = g.nry; f.nrx = g.nrx; f.nwg_x = g.nwg_x; f.nwg_total = g.nwg_total;
   f.SH = g.SH; f.SW = g.SW; f.NH = g.NH; f.CAP = g.CAP; f.p1_step = g.p1_step;
   f.lds_strip_off = g.lds_strip_off; f.lds_norm_off = g.lds_norm_off;
@@ -115,7 +118,8 @@ struct GroupGeom {
   int C, H, W, P, Hv, Wv, K;
   long long n_ref;
   int cnt_bits;  // ceil(log2(n_ref * K + 1)): headroom of the fixed-point sums
-  int s, r, nry, nrx;  // reference grid and window half-width of the plan
+  int s, r, nry, nrx;  // reference grid and candidate offsets before a reference
+  int wspan;           // window offsets -r .. -r + wspan
   // aggregation tiles: tb x tb references per workgroup, whose windows cover a region of
   // th x tw pixels accumulated in LDS (tb = 0: no tiling)
   int tb, th, tw, ntx, nty;

@@ -376,7 +376,7 @@ hipError_t launch_gather(const float* img, const int32_t* idx, float* groups, co
 void aggregate_tiling(GroupGeom& g) {
   g.tb = g.th = g.tw = g.ntx = g.nty = 0;
   for (int tb : {4, 2, 1}) {
-    const long long th = (long long)(tb - 1) * g.s + 2ll * g.r + g.P;
+    const long long th = (long long)(tb - 1) * g.s + g.wspan + g.P;
     if (th * th * 8 <= kTileLdsBytes) {
       g.tb = tb;
       g.th = g.tw = (int)th;

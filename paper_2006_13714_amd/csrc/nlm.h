@@ -88,7 +88,7 @@ nlm_fast(const float* __restrict__ img, const float* __restrict__ nrm,
 
   const int a_max = min(3, g.nry - 1 - RYw);
   const int b_max = min(3, g.nrx - 1 - RXw);
-  const int r2 = 2 * r;
+  const int r2 = g.wspan;  // window offsets -r .. -r + r2
   const int p16 = lane & 15;
   const int gp = lane >> 4;
   const int lane_off = CT::lane_off(gp);
@@ -115,7 +115,7 @@ nlm_fast(const float* __restrict__ img, const float* __restrict__ nrm,
   }
 
   const int qy_lo = max(0, ryw - r);
-  const int qy_hi = min(g.Hv - 1, ryw + s * a_max + r);
+  const int qy_hi = min(g.Hv - 1, ryw + s * a_max - r + r2);
   const int bl = lane_off + p16;
   // operand-B lane offset of the weighted sum: candidate 4t + gp of the tile, pixel
   // (row (p16 / 8) of the pair, column p16 % 8)

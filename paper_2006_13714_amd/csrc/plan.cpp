@@ -112,7 +112,7 @@ NormAux plan_aux(const bm_plan_s& p, void* ws) {
 
 bool fast_eligible(const bm_desc& d) {
   const int h2 = (d.patch + 1) / 2;
-  const int nt = (3 * d.stride + 2 * (d.window / 2) + 1 + kTileN - 1) / kTileN;
+  const int nt = (3 * d.stride + d.window + kTileN - 1) / kTileN;
   const int h2_min = d.precision == BM_PREC_FP32 ? 2 : 3;
   return d.channels <= 4 && h2 >= h2_min && h2 <= 4 && d.k <= 32 && nt >= 2 && nt <= 3;
 }
@@ -129,9 +129,9 @@ bm_status apply_config(const bm_desc& d, const TileCfg& c, int max_lds, bm_plan_
     return fail(BM_ENOTSUP, "%d waves per block exceed this kernel's limit", c.wy);
   if (!c.fast && d.precision != BM_PREC_FP32)
     return fail(BM_ENOTSUP, "split precision needs C <= 4, patch 5..8, K <= 32 and "
-                            "3*stride + window <= 48");
+                            "17 <= 3*stride + window <= 48");
   if (!c.fast && (d.flags & BM_FLAG_NCC))
-    return fail(BM_ENOTSUP, "NCC needs C <= 4, patch 3..8, K <= 32 and 3*stride + window <= 48");
+    return fail(BM_ENOTSUP, "NCC needs C <= 4, patch 3..8, K <= 32 and 17 <= 3*stride + window <= 48");
   p->geom = g;
   p->cfg = c;
   p->kr = kr_for(d.k);
@@ -175,9 +175,9 @@ static bm_status builtin_config(const bm_desc& d, int max_lds, bm_plan_s* p) {
   }
   if (d.precision != BM_PREC_FP32)
     return fail(BM_ENOTSUP, "split precision needs C <= 4, patch 5..8, K <= 32 and "
-                            "3*stride + window <= 48 (and the LDS to stage it)");
+                            "17 <= 3*stride + window <= 48 (and the LDS to stage it)");
   if (d.flags & BM_FLAG_NCC)
-    return fail(BM_ENOTSUP, "NCC needs C <= 4, patch 3..8, K <= 32 and 3*stride + window <= 48");
+    return fail(BM_ENOTSUP, "NCC needs C <= 4, patch 3..8, K <= 32 and 17 <= 3*stride + window <= 48");
   static const int shapes[][3] = {{2, 2, 64}, {1, 2, 64}, {2, 1, 64}, {1, 1, 64}, {1, 1, 32}};
   const int min_wg = 512;
   TileCfg chosen;

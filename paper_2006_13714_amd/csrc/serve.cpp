@@ -227,7 +227,7 @@ bm_status bm_submit(bm_server_t srv, const bm_desc* desc, const float* host_img,
   if (desc->window_depth > 0) return fail(BM_ENOTSUP, "the server takes 2D requests");
   if (desc->precision != BM_PREC_FP32 && !fast_eligible(*desc))
     return fail(BM_ENOTSUP, "split precision needs C <= 4, patch 5..8, K <= 32 and "
-                            "3*stride + window <= 48");
+                            "17 <= 3*stride + window <= 48");
   const char* why = "";
   st = srv->sch->submit(*desc, host_img, ticket, &why);
   if (st != BM_OK) return fail(st, "%s", why);

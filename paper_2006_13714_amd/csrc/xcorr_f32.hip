@@ -138,11 +138,12 @@ xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
   // scalars the inner loops use (kept out of the kernel-argument struct so that nothing
   // takes its address)
   const int s = g.s, r = g.r, CAP = g.CAP, K = g.K, W = g.W, NRS = g.NRS, RS = g.RS;
+  const int wsp = g.wspan;  // window offsets -r .. -r + wsp
   constexpr int TL = 2 * KR;  // per-lane list length of the bounding pass
   const int qy_lo = max(0, ryw - r);
-  const int qy_hi = min(g.Hv - 1, ryw + s * a_max + r);
+  const int qy_hi = min(g.Hv - 1, ryw + s * a_max - r + wsp);
   const int xs = rxw - r;  // first tile start (unclipped)
-  const int nt = (s * b_max + 2 * r + 1 + kTileN - 1) / kTileN;
+  const int nt = (s * b_max + wsp + 1 + kTileN - 1) / kTileN;
   const int tx_lo = xs < -(kTileN - 1) ? (-xs) / kTileN : 0;
   const int tx_hi = min(nt - 1, (g.Wv - 1 - xs) / kTileN);
   const int n_tx = tx_hi - tx_lo + 1;
@@ -188,11 +189,11 @@ xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
     Admit a;
     const float nc = nbase[(qy - SY0) * NRS + kTileN * tx];  // +inf off the valid range
     const int xrel = xs + kTileN * tx + p16 - rxw;
-    const bool yin = abs(qy - ryw - s * gp) <= r;
+    const bool yin = (unsigned)(qy - ryw - s * gp + r) <= (unsigned)wsp;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       a.d[v] = fmaf(-2.f, acc[v], nr[v] + nc);
-      a.pass[v] = yin & (abs(xrel - s * v) <= r) & (a.d[v] < th[v]);
+      a.pass[v] = yin & ((unsigned)(xrel - s * v + r) <= (unsigned)wsp) & (a.d[v] < th[v]);
     }
     return a;
   };
@@ -297,11 +298,11 @@ xcorr_topk_f32(const float* __restrict__ img, const float* __restrict__ nrm,
       [&](const f4& acc, int qy, int tx) __attribute__((always_inline)) {
         const float nc = nbase[(qy - SY0) * NRS + kTileN * tx];
         const int xrel = xs + kTileN * tx + p16 - rxw;
-        const bool yin = abs(qy - ryw - s * gp) <= r;
+        const bool yin = (unsigned)(qy - ryw - s * gp + r) <= (unsigned)wsp;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float d = fmaf(-2.f, acc[v], nr[v] + nc);
-          lane_insert<TL>(tl[v], (yin & (abs(xrel - s * v) <= r)) ? d : INFINITY);
+          lane_insert<TL>(tl[v], (yin & ((unsigned)(xrel - s * v + r) <= (unsigned)wsp)) ? d : INFINITY);
         }
         return 0;
       },

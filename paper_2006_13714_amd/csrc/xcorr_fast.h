@@ -186,7 +186,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
 
   const int a_max = min(3, g.nry - 1 - RYw);
   const int b_max = min(3, g.nrx - 1 - RXw);
-  const int P = g.P, r2 = 2 * r, W = g.W;
+  const int P = g.P, r2 = g.wspan, W = g.W;  // window offsets -r .. -r + r2
   const int p16 = lane & 15;  // operand A row / operand B column / output column
   const int gp = lane >> 4;   // lane group: 2x2 element of a step; output reference row
   const int lane_off = CT::lane_off(gp);
@@ -229,7 +229,7 @@ __device__ __forceinline__ void fast_block(const float* __restrict__ img,
   }
 
   const int qy_lo = max(0, ryw - r);
-  const int qy_hi = min(g.Hv - 1, ryw + s * a_max + r);
+  const int qy_hi = min(g.Hv - 1, ryw + s * a_max - r + r2);
   const int xs = rxw - r;  // first candidate column of the block
   const int bl = lane_off + p16;  // operand B lane offset within a strip row
   bool colok_t[NT];               // this lane's candidate column of tile t is a valid position

@@ -82,7 +82,8 @@ class BMShape:
     """One BM problem: image geometry plus the paper's BM parameters.
 
     ``patch`` is the patch side sqrt(n), ``stride`` the reference-grid stride, ``window``
-    the side of the square set of candidate offsets (odd), ``k`` the neighbours kept.
+    the side of the square set of candidate offsets (-floor(Wn/2) .. Wn - 1 - floor(Wn/2)
+    per axis), ``k`` the neighbours kept.
     """
 
     height: int
@@ -210,20 +211,19 @@ def video_voronoi(seed: int, q: int, H: int, W: int, sigma255: float,
     return vol.astype(np.float32)
 
 
-# paper: 256 x 256 x q, 6 x 6 x d patches, stride 1, 30 x 30 x c windows (the centred
-# window takes an odd side: 31)
-SHAPE_VIDEO = BMShape3D(256, 256, 20, 6, 1, 1, 31, 9, 16)
-SHAPE_MULTIMODAL = BMShape3D(256, 256, 6, 6, 3, 1, 31, 2, 16)
+# paper: 256 x 256 x q, 6 x 6 x d patches, stride 1, 30 x 30 x c windows
+SHAPE_VIDEO = BMShape3D(256, 256, 20, 6, 1, 1, 30, 9, 16)
+SHAPE_MULTIMODAL = BMShape3D(256, 256, 6, 6, 3, 1, 30, 2, 16)
 
 
 def video20() -> Workload:
-    """20 frames of 256 x 256, 6 x 6 x 1 blocks searched over 31 x 31 x 9 (seed 3)."""
+    """20 frames of 256 x 256, 6 x 6 x 1 blocks searched over 30 x 30 x 9 (seed 3)."""
     return Workload("video20_3d", SHAPE_VIDEO, video_voronoi(3, 20, 256, 256, 25.0), 3,
                     {"field": "voronoi 64 seeds moving (1, 2) px per frame", "sigma255": 25})
 
 
 def multimodal6() -> Workload:
-    """6 correlated planes of 256 x 256, 6 x 6 x 3 blocks searched over 31 x 31 x 2 (seed 4)."""
+    """6 correlated planes of 256 x 256, 6 x 6 x 3 blocks searched over 30 x 30 x 2 (seed 4)."""
     return Workload("multimodal6_3d", SHAPE_MULTIMODAL,
                     multichannel_voronoi(4, 256, 256, 6, 25.0), 4,
                     {"field": "voronoi base x gain U[0.7, 1.3] per plane", "sigma255": 25})

@@ -6,7 +6,7 @@ Runs bm_autotune for the shape classes of the library's workloads -- grayscale a
 images with 6x6 / 8x8 patches at stride 3 in a 39x39 window (K = 16), 2..4-channel 8x8
 patches, and 4-channel 8x8 patches at stride 4 in a 31x31 window (K = 32) -- in every
 precision form, over the three reference-grid size buckets per axis, plus the one-slab
-problems of the 3D search workloads (256 x 256, 6 x 6 patches, stride 1, 31 x 31 window,
+problems of the 3D search workloads (256 x 256, 6 x 6 patches, stride 1, 30 x 30 window,
 1 or 3 planes) -- each timed on a synthetic image of that class, and writes one
 "<class> | <configuration>" line per class.  --append-slabs tunes only the slab classes and
 appends them to an existing table.
@@ -20,8 +20,8 @@ import sys
 
 def slab_classes():
     """The one-slab 2D problems of the 3D search workloads (256 x 256 planes, 6 x 6 patches,
-    stride 1, 31 x 31 windows, K = 16; 1-plane and 3-plane blocks): 3D plans look these up."""
-    return [(256, 256, C, 6, 1, 31, 16, prec) for prec in ("fp32", "bf16x4", "fp16x3")
+    stride 1, 30 x 30 windows, K = 16; 1-plane and 3-plane blocks): 3D plans look these up."""
+    return [(256, 256, C, 6, 1, 30, 16, prec) for prec in ("fp32", "bf16x4", "fp16x3")
             for C in (1, 3)]
 
 

@@ -46,7 +46,7 @@ def test_status_strings():
 
 @pytest.mark.parametrize("field,value,needle", [
     ("height", 0, "height"), ("channels", 9, "channels"), ("patch", 0, "patch"),
-    ("patch", 17, "patch"), ("stride", 0, "stride"), ("window", 4, "odd"), ("window", 0, "odd"),
+    ("patch", 17, "patch"), ("stride", 0, "stride"), ("window", 0, "window must"), ("window", -3, "window must"),
     ("k", 0, "k must"), ("k", 65, "k must"), ("precision", 7, "precision"), ("flags", 8, "flag"),
 ])
 def test_invalid_descriptors_rejected_on_host(field, value, needle):

@@ -40,7 +40,9 @@ def assert_parity(v, P, d, s, Wn, c, K, idx, dist, precision, refs=None):
 @pytest.mark.parametrize("seed,q,H,W,P,d,s,Wn,c,K", [
     (1, 5, 40, 44, 6, 1, 2, 15, 3, 16), (2, 6, 36, 33, 5, 3, 3, 13, 2, 8),
     (3, 4, 30, 35, 8, 2, 1, 17, 4, 20), (4, 7, 29, 31, 3, 4, 2, 21, 9, 32),
-    (5, 3, 26, 23, 4, 3, 2, 13, 1, 12)])
+    (5, 3, 26, 23, 4, 3, 2, 13, 1, 12),
+    (8, 6, 40, 38, 6, 1, 1, 30, 9, 16),   # the paper's video setup shape: 30 x 30 x 9
+    (9, 5, 36, 41, 6, 3, 1, 30, 2, 16)])  # multi-modality: 6 x 6 x 3 blocks, 30 x 30 x 2
 def test_small_volumes_fp32(gpu, seed, q, H, W, P, d, s, Wn, c, K):
     banner(f"3d fp32 seed={seed} q={q} H={H} W={W} P={P} d={d} s={s} Wn={Wn} c={c} K={K}")
     v = np.random.default_rng(seed).uniform(0.0, 1.0, size=(q, H, W)).astype(np.float32)
@@ -51,7 +53,8 @@ def test_small_volumes_fp32(gpu, seed, q, H, W, P, d, s, Wn, c, K):
 
 @pytest.mark.parametrize("precision", ["fp16x3", "bf16x4"])
 @pytest.mark.parametrize("seed,q,H,W,P,d,s,Wn,c,K", [
-    (6, 5, 38, 41, 6, 1, 2, 15, 3, 16), (7, 6, 34, 30, 8, 2, 3, 13, 2, 24)])
+    (6, 5, 38, 41, 6, 1, 2, 15, 3, 16), (7, 6, 34, 30, 8, 2, 3, 13, 2, 24),
+    (10, 6, 40, 38, 6, 1, 1, 30, 9, 16)])
 def test_small_volumes_split(gpu, precision, seed, q, H, W, P, d, s, Wn, c, K):
     banner(f"3d {precision} seed={seed} q={q} P={P} d={d} c={c}")
     v = synth.video_voronoi(seed, q, H, W, 25.0, motion=(1, -1))

@@ -57,7 +57,8 @@ def bm_indices(x, P, s, Wn, K):
 
 
 @pytest.mark.parametrize("C,H,W,P,s,Wn,K", [(1, 64, 64, 8, 3, 21, 16), (3, 50, 61, 6, 2, 17, 8),
-                                             (4, 40, 44, 8, 4, 31, 20), (2, 33, 29, 5, 1, 15, 32)])
+                                             (4, 40, 44, 8, 4, 31, 20), (2, 33, 29, 5, 1, 15, 32),
+                                             (1, 50, 46, 6, 1, 30, 16), (3, 41, 38, 5, 3, 8, 9)])
 def test_gather_bitwise_and_reconstruction(gpu, C, H, W, P, s, Wn, K):
     banner(f"group gather/aggregate C={C} H={H} W={W} P={P} s={s} Wn={Wn} K={K}")
     rng = np.random.default_rng(C * 100 + P)

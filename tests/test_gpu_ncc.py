@@ -75,7 +75,8 @@ def test_rgbnir_sampled(gpu, precision):
 @pytest.mark.parametrize("seed,C,H,W,P,s,Wn,K,precision", [
     (1, 1, 50, 61, 8, 3, 21, 16, "fp32"), (2, 2, 41, 40, 5, 2, 11, 8, "fp32"),
     (3, 3, 64, 48, 6, 3, 17, 32, "fp16x3"), (4, 1, 33, 29, 3, 2, 15, 30, "fp32"),
-    (5, 4, 40, 44, 8, 4, 31, 20, "fp16x3"), (6, 2, 45, 70, 7, 3, 25, 17, "bf16x4")])
+    (5, 4, 40, 44, 8, 4, 31, 20, "fp16x3"), (6, 2, 45, 70, 7, 3, 25, 17, "bf16x4"),
+    (7, 1, 52, 48, 6, 1, 30, 16, "fp32"), (8, 3, 44, 46, 6, 2, 30, 16, "fp16x3")])
 def test_edge_shapes_with_zero_regions(gpu, seed, C, H, W, P, s, Wn, K, precision):
     """Random signed images with a zero block (zero-norm references and candidates)."""
     banner(f"ncc edge seed={seed} C={C} H={H} W={W} P={P} s={s} Wn={Wn} K={K} {precision}")

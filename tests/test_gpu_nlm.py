@@ -71,7 +71,8 @@ def test_rgbnir_sampled(gpu):
 
 @pytest.mark.parametrize("seed,C,H,W,P,s,Wn,b", [
     (1, 1, 50, 61, 8, 3, 21, 1.5), (2, 2, 41, 40, 5, 2, 13, 1.0), (3, 3, 64, 48, 6, 3, 17, 2.0),
-    (4, 1, 33, 29, 3, 2, 15, 0.6), (5, 4, 40, 44, 8, 4, 31, 3.0), (6, 2, 45, 70, 7, 3, 25, 1.8)])
+    (4, 1, 33, 29, 3, 2, 15, 0.6), (5, 4, 40, 44, 8, 4, 31, 3.0), (6, 2, 45, 70, 7, 3, 25, 1.8),
+    (7, 1, 52, 48, 6, 1, 30, 1.2), (8, 2, 41, 44, 5, 2, 12, 1.0)])
 def test_edge_shapes(gpu, seed, C, H, W, P, s, Wn, b):
     banner(f"nlm edge seed={seed} C={C} H={H} W={W} P={P} s={s} Wn={Wn} b={b}")
     rng = np.random.default_rng(seed)

@@ -38,7 +38,43 @@ def test_worked_example_exact(gpu):
     parity.check_exact(idx, dist, oidx, odist)
 
 
+def test_even_window_worked_example_exact(gpu):
+    """The hand-derived even-window example (offsets -1 and 0 for a window of 2)."""
+    banner("worked example even window 4x5")
+    x = (5 * np.arange(4)[:, None] + np.arange(5)[None, :]).astype(np.float32)[None]
+    idx, dist = run(x, 2, 1, 2, 4)
+    oidx, odist = O.bm(x, 2, 1, 2, 4)
+    parity.check_exact(idx, dist, oidx, odist)
+    assert idx[6].tolist() == [7, 6, 2, 1] and dist[6].tolist() == [0.0, 4.0, 100.0, 144.0]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16x3", "bf16x4"])
+@pytest.mark.parametrize("seed,C,H,W,P,s,Wn,K", [
+    (21, 1, 72, 70, 6, 1, 30, 16),   # the paper's runtime setup: 6x6, stride 1, 30x30
+    (22, 3, 48, 52, 6, 2, 30, 16),
+    (23, 1, 40, 37, 8, 3, 4, 9),
+    (24, 2, 45, 50, 5, 1, 2, 8),
+    (25, 4, 40, 44, 8, 4, 16, 20),
+    (26, 1, 60, 41, 7, 3, 36, 32),
+])
+def test_even_windows(gpu, precision, seed, C, H, W, P, s, Wn, K):
+    banner(f"even window {precision} seed={seed} C={C} H={H} W={W} P={P} s={s} Wn={Wn} K={K}")
+    x = synth.random_image(seed, C, H, W)
+    if precision != "fp32" and 3 * s + Wn < 17:
+        # the split forms run in the specialised kernel only, whose candidate span per
+        # reference block is 17..48 columns (two or three 16-wide tiles)
+        bm = ensure_built()
+        with pytest.raises(bm.BMError) as ei:
+            run(x, P, s, Wn, K, precision)
+        assert ei.value.status == bm.BM_ENOTSUP
+        return
+    idx, dist = run(x, P, s, Wn, K, precision)
+    assert idx.shape == (len(O.ref_list(H, W, P, s)), K)
+    print(assert_parity(x, P, s, Wn, K, idx, dist))
+
+
 @pytest.mark.parametrize("a,b,C,P,s,Wn,K", [(1, 2, 1, 8, 3, 21, 16), (2, 2, 1, 4, 2, 9, 30),
+                                             (1, 3, 1, 6, 1, 30, 24), (2, 1, 2, 4, 3, 8, 12),
                                              (1, 1, 3, 6, 3, 13, 64), (0, 1, 2, 5, 1, 7, 20)])
 def test_ramp_exact_with_ties(gpu, a, b, C, P, s, Wn, K):
     banner(f"ramp a={a} b={b} C={C} P={P} s={s} Wn={Wn} K={K}")
