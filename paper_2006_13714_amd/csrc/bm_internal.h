@@ -20,10 +20,10 @@ constexpr int kSplitRW = 64;      // LDS row stride (words) of the specialised s
 constexpr int split_rw(int C) { return C == 1 ? 55 : kSplitRW; }
 
 // Output tile of the norm pass.  Tile (tx, ty) stages the input window rows
-// [8 ty, 8 ty + 8 + P - 1) x columns [32 tx, 32 tx + 32 + P - 1), clipped to the image,
-// so every pixel lies in the tile (min(x / 32, ntx - 1), min(y / 8, nty - 1)).
-constexpr int kNormTX = 32;
-constexpr int kNormTY = 8;
+// [16 ty, 16 ty + 16 + P - 1) x columns [64 tx, 64 tx + 64 + P - 1), clipped to the image,
+// so every pixel lies in the tile (min(x / 64, ntx - 1), min(y / 16, nty - 1)).
+constexpr int kNormTX = 64;
+constexpr int kNormTY = 16;
 
 // Geometry of one fused cross-term / distance / top-K launch.  All sizes in elements.
 struct XcGeom {

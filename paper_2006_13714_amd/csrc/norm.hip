@@ -4,14 +4,15 @@
 // h_X (.) h_X (Sec. III-B, the normalisation vector h_X; used by Lemma 2).  center_c comes
 // from the centring pass when centring is on (centers[c]); otherwise it is zero.
 //
-// One workgroup of 256 threads produces a kNormTY x kNormTX output tile (one output per
-// thread; 8 x 32, so a 512 x 512 image gives 1024 workgroups and every compute unit has
-// several to overlap their load / sum / store phases).  It stages the (TY+P-1) x (TX+P-1)
-// input window of one channel in LDS with coalesced row loads, forms the horizontal P-tap
-// sums of squares, then the vertical P-tap sums, and accumulates over channels.  Sums are
-// direct (no prefix or summed-area tables, whose rounding grows with the image) and
-// carried in float64, so every output is the float32 rounding of the exact norm.  Each
-// input element is read once from HBM (halos come from L2) and each output written once.
+// One workgroup of 256 threads produces a kNormTY x kNormTX output tile (16 x 64: four
+// outputs per thread, one column and four rows).  Per channel it stages the
+// (TY+P-1) x (TX+P-1) input window in LDS (each thread keeps twelve loads in flight, in
+// rows of 32 consecutive columns, no index divisions), adds the horizontal P-tap sums of
+// squares of its columns into per-thread float64 accumulators (channels summed there),
+// and after the last channel forms the vertical P-tap sums.  Sums are direct (no prefix or
+// summed-area tables, whose rounding grows with the image) and carried in float64, so every
+// output is the float32 rounding of the exact norm.  Each input element is read once from
+// HBM (halos come from L2) and each output written once.
 //
 // For the bfloat16 split form the staged values are first rounded to hi + lo (split16.h),
 // so the map holds the norms of the rounded image that the form's cross term multiplies.
@@ -30,12 +31,15 @@
 namespace bmk {
 
 constexpr int kMaxP = 16;
+constexpr int kStageRows = kNormTY + kMaxP - 1;  // 31
+constexpr int kStageCols = kNormTX + kMaxP - 1;  // 79
+constexpr int kStageRS = 80;                     // LDS row stride (floats)
 
-static_assert(kNormTX * kNormTY == 256, "one output per thread");
+static_assert(kNormTX == 64 && kNormTY == 16, "thread layout below");
 
 struct NormLds {
-  float tile[kNormTY + kMaxP - 1][kNormTX + kMaxP];
-  double hs[kNormTY + kMaxP - 1][kNormTX];
+  float tile[kStageRows][kStageRS];
+  double hs[kStageRows][kNormTX];
   float red[4];
 };
 
@@ -47,41 +51,71 @@ __device__ __forceinline__ void norm_tile(const float* __restrict__ img, float* 
   const int oy0 = by * kNormTY;
   const int rows = kNormTY + g.P - 1;
   const int cols = kNormTX + g.P - 1;
-  const int orow = t / kNormTX, ocol = t - (t / kNormTX) * kNormTX;  // this thread's output
-  double acc = 0.0;
+  // staging layout: 8 rows x 32 columns of threads, 4 x 3 loads each
+  const int ly = t >> 5, lx = t & 31;
+  // horizontal sums: column hc, rows hr + 4 k; vertical sums: column hc, rows 4 vr .. + 3
+  const int hc = t & 63, hr = t >> 6;
+  double hacc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) hacc[k] = 0.0;
   float vmax = 0.f;
 
-  for (int c = 0; c < g.C; ++c) {
+  // channel c's loads are issued before channel c - 1's sums, so their latency overlaps
+  float v[4][3];
+  auto load = [&](int c) __attribute__((always_inline)) {
     const float* plane = img + (size_t)c * g.H * g.W;
     const float cc = centers ? centers[c] : 0.f;
-    for (int i = t; i < rows * cols; i += 256) {
-      const int rr = i / cols, xx = i - (i / cols) * cols;
-      const int y = oy0 + rr, x = ox0 + xx;
-      float v = 0.f;
-      if (y < g.H && x < g.W) v = plane[(size_t)y * g.W + x] - cc;
-      if (g.round_bf16) v = bf16_split_value(v);
-      sh.tile[rr][xx] = v;
-      vmax = fmaxf(vmax, fabsf(v));
-    }
-    __syncthreads();
-    for (int i = t; i < rows * kNormTX; i += 256) {
-      const int rr = i / kNormTX, cx = i - (i / kNormTX) * kNormTX;
-      double s = 0.0;
-      for (int m = 0; m < g.P; ++m) {
-        const double v = (double)sh.tile[rr][cx + m];
-        s += v * v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int y = oy0 + ly + 8 * i, x = ox0 + lx + 32 * j;
+        const bool ok = (ly + 8 * i < rows) & (lx + 32 * j < cols) & (y < g.H) & (x < g.W);
+        v[i][j] = ok ? plane[(size_t)y * g.W + x] - cc : 0.f;
       }
-      sh.hs[rr][cx] = s;
-    }
+  };
+  load(0);
+  for (int c = 0; c < g.C; ++c) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        float x = v[i][j];
+        if (g.round_bf16) x = bf16_split_value(x);
+        vmax = fmaxf(vmax, fabsf(x));
+        if ((ly + 8 * i < kStageRows) & (lx + 32 * j < kStageRS))
+          sh.tile[ly + 8 * i][lx + 32 * j] = x;
+      }
     __syncthreads();
-    double s = 0.0;
-    for (int l = 0; l < g.P; ++l) s += sh.hs[orow + l][ocol];
-    acc += s;
+    if (c + 1 < g.C) load(c + 1);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int r = hr + 4 * k;
+      if (r < rows) {
+        double s = 0.0;
+        for (int m = 0; m < g.P; ++m) {
+          const double x = (double)sh.tile[r][hc + m];
+          s = fma(x, x, s);
+        }
+        hacc[k] += s;
+      }
+    }
     __syncthreads();
   }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (hr + 4 * k < rows) sh.hs[hr + 4 * k][hc] = hacc[k];
+  __syncthreads();
   {
-    const int oy = oy0 + orow, ox = ox0 + ocol;
-    if (oy < g.Hv && ox < g.Wv) out[(size_t)oy * g.Wv + ox] = (float)acc;
+    const int ox = ox0 + hc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int orow = 4 * hr + q;
+      double s = 0.0;
+      for (int l = 0; l < g.P; ++l) s += sh.hs[orow + l][hc];
+      const int oy = oy0 + orow;
+      if (oy < g.Hv && ox < g.Wv) out[(size_t)oy * g.Wv + ox] = (float)s;
+    }
   }
   if (amax) {
 #pragma unroll
