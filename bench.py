@@ -44,7 +44,8 @@ sys.path.insert(0, ROOT)
 METRIC = "ref patches/s (top-16, 8x8 patch, 39x39 window) vs plain FP32; p50/p99 latency"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x4": 2500.0, "fp16x3": 2500.0}  # dense matrix-core peaks
 DTYPE = {"fp32": "f32", "bf16x4": "bf16x4->f32", "fp16x3": "f16x3->f32"}
-_FAST = ["xcorr_fast.h", "contract.h", "select.h", "topk.h", "bm_internal.h", "split16.h"]
+_FAST = ["xcorr_fast.h", "xcorr_lane.h", "xcorr_common.h", "contract.h", "select.h", "topk.h",
+         "bm_internal.h", "split16.h"]
 KERNEL_SOURCES = {"fp32": _FAST, "bf16x4": _FAST, "fp16x3": _FAST}
 
 

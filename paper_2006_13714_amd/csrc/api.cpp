@@ -140,9 +140,11 @@ void fill_geom(const bm_desc& d, int wy, int wx, int cap, bool fast, XcGeom& g,
   const int strip_bytes = rows_per_img_row * g.SH * g.RS * 4;
   // the specialised BM kernels read candidate norms from the norm map (L2); the generic
   // kernel and non-local means stage them in LDS
-  const int norm_bytes = (fast && !fast_norm_strip) ? 0 : g.NH * g.NRS * 4;
+  const int norm_bytes =
+      (fast && !fast_norm_strip && !lane_norm_strip(d.channels)) ? 0 : g.NH * g.NRS * 4;
   int buf_bytes = nw * 16 * cap * 8;
   if (fast) {
+    buf_bytes = nw * (16 * cap * 8 + 64);  // per wave: cap entries per reference + counters
     const int kr = d.k <= 16 ? 1 : 2;
     const int tl_bytes = nw * 4 * (2 * kr) * 64 * 4 + 4 * 64 * 4;  // bounding lists + bounds
     const int list_bytes = nw * 4 * kr * 64 * 8;        // final-list exchange
@@ -243,13 +245,13 @@ bm_status bm_plan(const bm_desc* desc, bm_plan_t* out) {
       // configuration was sized without that strip, so if it no longer fits, take the
       // largest block (waves, then buffer capacity) at or below it that does
       XcGeom g3;
-      fill_geom(p->desc, p->cfg.wy, 1, p->cfg.cap, true, g3, true);
+      fill_geom(p->desc, p->cfg.wy, 1, p->cfg.cap, true, g3);
       if (g3.lds_bytes > max_lds) {
         bool found = false;
         for (int ws = p->cfg.wy; ws >= 1 && !found; ws = ws > 1 ? ws / 2 : 0)
           for (int cap : {p->cfg.cap, 48, 32}) {
             if (cap > p->cfg.cap || (ws == p->cfg.wy && cap == p->cfg.cap)) continue;
-            fill_geom(p->desc, ws, 1, cap, true, g3, true);
+            fill_geom(p->desc, ws, 1, cap, true, g3);
             if (g3.lds_bytes <= max_lds) {
               p->cfg.wy = ws;
               p->cfg.cap = cap;
@@ -257,7 +259,7 @@ bm_status bm_plan(const bm_desc* desc, bm_plan_t* out) {
               break;
             }
           }
-        if (!found) fill_geom(p->desc, p->cfg.wy, 1, p->cfg.cap, true, g3, true);
+        if (!found) fill_geom(p->desc, p->cfg.wy, 1, p->cfg.cap, true, g3);
       }
       g3.p1_step = p->cfg.p1;
       if (g3.lds_bytes > max_lds) {

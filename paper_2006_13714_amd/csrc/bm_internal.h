@@ -93,6 +93,13 @@ constexpr int fast_max_waves(int prec, int C) { return (prec == 0 && C == 4) ? 4
 // keep two per SIMD; the other classes keep several 4-wave workgroups per compute unit.
 constexpr int fast_default_waves(int prec, int C) { return (prec != 0 && C >= 2) ? 8 : 4; }
 
+// Whether the specialised kernel stages the candidate norms in LDS with the pixel strip
+// (per slab in 3D) or reads them from the norm map one tile ahead: multi-channel blocks,
+// which take one or two workgroups per compute unit anyway and sweep large maps, stage
+// them; one-channel blocks read the (L2-resident) map, which leaves LDS for more
+// workgroups per compute unit.
+constexpr bool lane_norm_strip(int C) { return C >= 2; }
+
 // Kernel tier of the persistent batch launch for a precision form and channel count, and
 // the largest workgroup (waves) of each tier: float32 1 channel (tier 3), 2..3 channels (0),
 // 4 channels (1); split forms 1 channel (0), 2..4 channels (2).
@@ -104,7 +111,7 @@ constexpr int batch_max_waves(int tier) { return tier == 2 ? 8 : 4; }
 // image's norm map a row ahead, as the single-image kernels do): the split forms' tiers
 // read the map (less LDS per block, more blocks per compute unit), the float32 tiers,
 // which gain nothing from it, keep the strip.
-constexpr bool batch_norm_strip(int prec, int tier) { return (void)tier, prec == 0; }
+constexpr bool batch_norm_strip(int prec, int tier) { return (void)prec, (void)tier, false; }
 
 struct NormGeom {
   int H, W, C, P, Hv, Wv;

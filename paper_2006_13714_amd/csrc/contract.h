@@ -129,6 +129,30 @@ struct CtF32 {
     else return acc[0] + acc[1];
   }
 
+  // The same chain with the candidates as the row operand: lane (g, p) receives the cross
+  // terms of candidates 4 g .. 4 g + 3 of the tile with reference p.  The first accumulator
+  // starts from `init`; the accumulators are returned raw and added by combine() one tile
+  // later, so nothing waits for the matrix ops here.
+  static constexpr int NACC_T = NACC;
+  static constexpr bool kInitInChain = true;
+  __device__ static void chain_t(const AReg (&A)[NS], const float (&cur)[NB], float (&nxt)[NB],
+                                 const uint32_t* strip, int nb, int, const f4& init,
+                                 f4 (&acc)[NACC_T]) {
+    const float* s = reinterpret_cast<const float*>(strip);
+    acc[0] = init;
+#pragma unroll
+    for (int q = 1; q < NACC; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+      acc[t % NACC] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[t], A[t], acc[t % NACC], 0, 0, 0);
+      nxt[t] = s[nb + off(t)];
+    }
+  }
+  __device__ static f4 combine(const f4 (&acc)[NACC_T]) {
+    if constexpr (NACC == 4) return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    else return acc[0] + acc[1];
+  }
+
   __device__ static void schedule() {
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
@@ -295,6 +319,34 @@ struct CtSplit {
     for (int b = 0; b < NKB; ++b) acc = mfma(A[2 * b], cur[2 * b], acc);  // hi * hi
     return acc;
   }
+
+  // The same chain with the candidates as the row operand: lane (g, p) receives the cross
+  // terms of candidates 4 g .. 4 g + 3 of the tile with reference p.  The chain starts
+  // from zero (small products first, as above); the caller adds its starting value one
+  // tile later, so nothing waits for the matrix ops here.
+  static constexpr int NACC_T = 1;
+  static constexpr bool kInitInChain = false;
+  __device__ static void chain_t(const AReg (&A)[2 * NKB], const u4 (&cur)[NB], u4 (&nxt)[NB],
+                                 const uint32_t* strip, int nb, int lo, const f4&,
+                                 f4 (&out)[NACC_T]) {
+    const uint32_t* sh = strip + nb;
+    const uint32_t* sl = strip + nb + lo;
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < NKB; ++b) {
+      if constexpr (kLL) acc = mfma(cur[2 * b + 1], A[2 * b + 1], acc);  // lo * lo
+      acc = mfma(cur[2 * b + 1], A[2 * b], acc);      // hi (reference) * lo (candidate)
+      acc = mfma(cur[2 * b], A[2 * b + 1], acc);      // lo * hi
+#pragma unroll
+      for (int i = 0; i < 4; ++i) nxt[2 * b][i] = sh[woff(b, i)];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) nxt[2 * b + 1][i] = sl[woff(b, i)];
+    }
+#pragma unroll
+    for (int b = 0; b < NKB; ++b) acc = mfma(cur[2 * b], A[2 * b], acc);  // hi * hi
+    out[0] = acc;
+  }
+  __device__ static f4 combine(const f4 (&acc)[NACC_T]) { return acc[0]; }
 
   __device__ static void schedule() {
 #pragma unroll

@@ -27,8 +27,9 @@ __device__ __forceinline__ void batch_block(const BatchXc& r, int blk, unsigned 
     // split forms need patch sides 5..8; the host never forms such items
     (void)r, (void)blk, (void)lds;
   } else {
-    fast_block<CtFor<PREC, C, H2>, C, KR, NT, false, NSTRIP>(r.img, r.nrm, r.centers, r.amax,
-                                                             r.idx, r.dist, r.g, blk, lds);
+    (void)NSTRIP;
+    lane_block<CtFor<PREC, C, H2>, C, KR, NT, false>(r.img, r.nrm, r.centers, r.amax, r.idx,
+                                                     r.dist, r.g, blk, lds);
   }
 }
 
