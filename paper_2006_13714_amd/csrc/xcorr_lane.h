@@ -411,13 +411,14 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
   // reference 4 g + R), then lower each lane's threshold to its reference's list K-th
   // distance.
   bool flushed = false;  // a buffer flush happened in the selecting sweep (wave-uniform)
+  constexpr int kFlushedBit = 1 << 24, kCountMask = kFlushedBit - 1;
   auto flush = [&]() __attribute__((always_inline)) {
     flushed = true;
     float kth[4];
 #pragma unroll
     for (int R = 0; R < 4; ++R) {
       const int p = 4 * gp + R;
-      const int n = wcnt[p];
+      const int n = wcnt[p] & kCountMask;
       for (int e0 = 0; __any(e0 < n); e0 += 16) {
         const int e = e0 + p16;
         float cd = INFINITY;
@@ -482,7 +483,16 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
   //      the owner of round R (wave R mod S) merges every wave's buffered entries of its
   //      four references at once.  Otherwise each wave flushes its buffers into its lists
   //      and the owner merges the other waves' (sorted) lists.
-  const bool any_flushed = S > 1 ? (__syncthreads_or(flushed) != 0) : true;
+  //      The flag travels in a high bit of each wave's counters (no LDS beyond the layout's).
+  if (flushed && lane < 16) wcnt[lane] |= kFlushedBit;
+  bool any_flushed = true;
+  if (S > 1) {
+    __syncthreads();
+    const size_t wst = (size_t)16 * CAP * 8 + 64;
+    int fl = 0;
+    for (int w = 0; w < S; ++w) fl |= reinterpret_cast<const int*>(bufs + w * wst + (size_t)16 * CAP * 8)[0];
+    any_flushed = (__builtin_amdgcn_readfirstlane(fl) & kFlushedBit) != 0;
+  }
   if (!any_flushed) {
     const size_t wstride = (size_t)16 * CAP * 8 + 64;
 #pragma unroll
@@ -493,7 +503,7 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
       int tot = 0;
       for (int w = 0; w < S; ++w) {
         off[w] = tot;
-        tot += reinterpret_cast<const int*>(bufs + w * wstride + (size_t)16 * CAP * 8)[p];
+        tot += reinterpret_cast<const int*>(bufs + w * wstride + (size_t)16 * CAP * 8)[p] & kCountMask;
       }
       for (int e0 = 0; __any(e0 < tot); e0 += 16) {
         const int e = e0 + p16;
