@@ -15,9 +15,10 @@ the reported form), timed with HIP events on its own launch stream, against the 
 matrix peak and the peak measured in the same run (`peaks_measured`: a matrix-op loop per
 form and a streaming copy); `executed` adds the matrix/vector pipe utilisation from the
 committed counter summary when it matches the current sources.  The same line carries
-short forms of the other workloads: `batch64` (the 64-image uneven batch, one
-bm_match_batch call per step in each form, and the same images as 64 bm_match calls),
-`serving` (Poisson streams through bm_submit / bm_poll at two request rates, bfloat16
+short forms of the other workloads: `rgbnir1024` (the split-precision workload, 1024 x
+1024 x 4 with joint 8 x 8 x 4 patches, every form, with its accuracy), `batch64` (the
+64-image uneven batch, one bm_match_batch call per step in each form, and the same images
+as 64 bm_match calls), `serving` (Poisson streams through bm_submit / bm_poll at two request rates, bfloat16
 split; `latency_ms` then holds the request latency of the lower rate), and `cpu_baseline`
 (the FP64 oracle on this host: one core on a bounded sample, all cores on the whole
 image) with `accuracy`, the error of every form against the oracle on a seeded sample.
@@ -95,14 +96,16 @@ def _oracle_refs(args):
     return len(refs)
 
 
-def cpu_baseline(img, sh, budget_s: float, forms=None):
+def cpu_baseline(img, sh, budget_s: float, forms=None, extra=None):
     """FP64 oracle timed on this host, and the accuracy of every GPU form against it.
 
     One core: every second reference in row-major order until budget_s has passed.  All
     cores: every reference of the image, sliced over a process pool of one worker per
     available core (workers started and warmed before the timed map).  Accuracy: the
     oracle's rows for a seeded sample of references, against each form's result (tolerance
-    rule 1e-4 with the 1e-2 (N_i + N_j) floor; set rule)."""
+    rule 1e-4 with the 1e-2 (N_i + N_j) floor; set rule).  `extra` maps another workload's
+    name to (image, shape, {form: (idx, dist)}); its accuracy is reported the same way on
+    a seeded sample plus the first and last reference rows and columns."""
     import multiprocessing as mp
     import numpy as np
     from oracle import bm_oracle as O
@@ -163,6 +166,26 @@ def cpu_baseline(img, sh, budget_s: float, forms=None):
         out["accuracy"] = {"refs": int(len(refs)),
                            "sample": "1000 seeded references (seed 11) plus the first and "
                                      "last reference rows", "forms": acc}
+    for name, (ximg, xsh, xforms) in (extra or {}).items():
+        from tests import parity
+        nry = (xsh.height - xsh.patch) // xsh.stride + 1
+        nrx = (xsh.width - xsh.patch) // xsh.stride + 1
+        grid = np.arange(xsh.n_ref).reshape(nry, nrx)
+        rng = np.random.default_rng(12)
+        refs = np.unique(np.concatenate([rng.choice(xsh.n_ref, 600, replace=False),
+                                         grid[0], grid[-1], grid[:, 0], grid[:, -1]]))
+        t0 = time.perf_counter()
+        head = parity.OracleHead(ximg, xsh.patch, xsh.stride, xsh.window, xsh.k, refs=refs)
+        acc = {}
+        for f, (idx, dist) in xforms.items():
+            rep = head.check(idx[refs], dist[refs])
+            r = rep.summary()
+            r["within_rule"] = rep.tolerant_mismatch == 0 and rep.order_violations == 0
+            acc[f] = r
+        out.setdefault("accuracy_other", {})[name] = {
+            "refs": int(len(refs)), "oracle_s": time.perf_counter() - t0,
+            "sample": "600 seeded references (seed 12) plus every border reference",
+            "forms": acc}
     return out
 
 
@@ -459,6 +482,8 @@ def main():
             "p50_ms": quantile(sf, 0.5), "p99_ms": quantile(sf, 0.99)}
         for f, (pf, wf, nf, xf, sf, _) in ncc.items()}
     out["volumes"] = volumes(bm, synth, torch, max(3, args.steps // 20), 2)
+    rgb, rgb_outs = rgbnir_summary(bm, synth, torch, max(5, args.steps // 10))
+    out["rgbnir1024"] = rgb
     # measured attainable peaks beside the published ones
     peaks = {f: bm.bm_peak_mfma(f, 0) for f in PEAK_TFLOPS}
     peaks32 = {f: bm.bm_peak_mfma(f, 1) for f in PEAK_TFLOPS}
@@ -500,13 +525,47 @@ def main():
     out["plain_fp32"] = {"value": v32, "speedup": value / v32}
     if args.cpu_budget > 0:
         outs = {f: (r[5][0].cpu().numpy(), r[5][1].cpu().numpy()) for f, r in results.items()}
-        out["cpu_baseline"] = cpu_baseline(w.image, sh, args.cpu_budget, outs)
+        out["cpu_baseline"] = cpu_baseline(w.image, sh, args.cpu_budget, outs,
+                                           {"rgbnir1024": rgb_outs})
         acc = out["cpu_baseline"].get("accuracy", {}).get("forms", {})
         out["accuracy"] = acc
+        other = out["cpu_baseline"].get("accuracy_other", {}).get("rgbnir1024")
+        if other:
+            rgb["accuracy"] = other
         if prec in acc and not acc[prec]["within_rule"]:
             out["plain_fp32"]["speedup"] = None
             out["plain_fp32"]["note"] = f"{prec} is outside the 1e-4 rule on the sample"
     print(json.dumps(out), flush=True)
+
+
+def rgbnir_summary(bm, synth, torch, steps):
+    """The split-precision workload (1024 x 1024 x 4, joint 8 x 8 x 4 patches, stride 4,
+    31 x 31 window, K = 32): every form timed as in the headline (bm_norms + bm_cross_topk
+    per step, HIP events); returns the summary and each form's outputs (for accuracy)."""
+    w = synth.rgbnir1024()
+    sh = w.shape
+    img_t = torch.from_numpy(w.image).to("cuda:0")
+    pairs = pair_count(sh.height, sh.width, sh.patch, sh.stride, sh.window)
+    flops = 2.0 * sh.patch * sh.patch * sh.channels * pairs
+    res = {"workload": w.name, "height": sh.height, "width": sh.width,
+           "channels": sh.channels, "patch": sh.patch, "stride": sh.stride,
+           "window": sh.window, "k": sh.k, "n_ref": sh.n_ref, "pairs": pairs,
+           "algorithmic_flops": flops, "forms": {}}
+    outs = {}
+    for prec in ["fp32", "bf16x4", "fp16x3"]:
+        plan, wall, norm_ms, xc_ms, step_ms, (idx, dist) = run_form(
+            bm, torch, img_t, sh, prec, steps, 2)
+        xa = sum(xc_ms) / len(xc_ms) / 1e3
+        res["forms"][prec] = {"value": sh.n_ref * steps / wall,
+                              "ms_per_step": wall / steps * 1e3, "cross_topk_ms": xa * 1e3,
+                              "norm_ms": sum(norm_ms) / len(norm_ms),
+                              "config": bm.bm_plan_config(plan)[0],
+                              "roofline_frac": flops / xa / 1e12 / PEAK_TFLOPS[prec]}
+        outs[prec] = (idx.cpu().numpy(), dist.cpu().numpy())
+    v32 = res["forms"]["fp32"]["value"]
+    for prec in res["forms"]:
+        res["forms"][prec]["speedup_vs_fp32"] = res["forms"][prec]["value"] / v32
+    return res, (w.image, sh, outs)
 
 
 SERVE_FORM = "bf16x4"

@@ -135,6 +135,10 @@ struct CtF32 {
   // later, so nothing waits for the matrix ops here.
   static constexpr int NACC_T = NACC;
   static constexpr bool kInitInChain = true;
+  // the bounding sweep runs the same chain (bit-identical distances): no inflation
+  static constexpr bool kBoundChain = false;
+  static constexpr float kBoundRel = 0.f, kBoundAbs = 0.f;
+  template <bool BOUND = false>
   __device__ static void chain_t(const AReg (&A)[NS], const float (&cur)[NB], float (&nxt)[NB],
                                  const uint32_t* strip, int nb, int, const f4& init,
                                  f4 (&acc)[NACC_T]) {
@@ -153,6 +157,7 @@ struct CtF32 {
     else return acc[0] + acc[1];
   }
 
+  template <bool BOUND = false>
   __device__ static void schedule() {
 #pragma unroll
     for (int t = 0; t < NS; ++t) {
@@ -324,8 +329,23 @@ struct CtSplit {
   // terms of candidates 4 g .. 4 g + 3 of the tile with reference p.  The chain starts
   // from zero (small products first, as above); the caller adds its starting value one
   // tile later, so nothing waits for the matrix ops here.
+  //
+  // BOUND (bfloat16 only): the bounding sweep's shorter chain, without lo * lo.  The values
+  // v = hi + lo of the bfloat16 form have |lo| <= 2^-8 (1 + 2^-7) |v|, so by Cauchy-Schwarz
+  // and ||v_i|| ||v_j|| <= (V_i + V_j) / 2 (V = ||v||^2, the norm map's value) the dropped
+  // products sum to at most 2^-17 (1 + 2^-6) (V_i + V_j); the float32 accumulation of each
+  // chain (at most 4 n <= 1024 roundings of sums of products bounded as above) errs by at
+  // most 2^-15 (1 + 2^-6) (V_i + V_j).  A distance d = ... - 2 C therefore moves by less
+  // than 2^-12.8 (V_i + V_j) < kBoundRel (V_i + V_j), which the bounding sweep adds to its
+  // distances.  (For float16 the one product hi * hi
+  // needs a margin of about 2^-10 (V_i + V_j), which admitted more candidates than the
+  // saved products gained: it keeps the selecting sweep's chain.)
   static constexpr int NACC_T = 1;
   static constexpr bool kInitInChain = false;
+  static constexpr bool kBoundChain = kLL;
+  static constexpr float kBoundRel = kLL ? 0x1p-12f : 0.f;
+  static constexpr float kBoundAbs = 0.f;
+  template <bool BOUND = false>
   __device__ static void chain_t(const AReg (&A)[2 * NKB], const u4 (&cur)[NB], u4 (&nxt)[NB],
                                  const uint32_t* strip, int nb, int lo, const f4&,
                                  f4 (&out)[NACC_T]) {
@@ -334,7 +354,7 @@ struct CtSplit {
     f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int b = 0; b < NKB; ++b) {
-      if constexpr (kLL) acc = mfma(cur[2 * b + 1], A[2 * b + 1], acc);  // lo * lo
+      if constexpr (kLL && !BOUND) acc = mfma(cur[2 * b + 1], A[2 * b + 1], acc);  // lo * lo
       acc = mfma(cur[2 * b + 1], A[2 * b], acc);      // hi (reference) * lo (candidate)
       acc = mfma(cur[2 * b], A[2 * b + 1], acc);      // lo * hi
 #pragma unroll
@@ -348,9 +368,11 @@ struct CtSplit {
   }
   __device__ static f4 combine(const f4 (&acc)[NACC_T]) { return acc[0]; }
 
+  template <bool BOUND = false>
   __device__ static void schedule() {
+    constexpr int NSB = (BOUND && kLL) ? 3 * NKB : NS;  // matrix ops of the chain
 #pragma unroll
-    for (int t = 0; t < NS; ++t) {
+    for (int t = 0; t < NSB; ++t) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one matrix op
       __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // up to two vector ops
       __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);  // up to three LDS reads

@@ -238,8 +238,11 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
   // One sweep over rows first, first + stride, ... <= last of this wave.  The previous
   // tile's scores go to `arith(sc, tx, qy)` (branch-free, interleaved with this tile's
   // matrix ops) and its result to `post(res, tx, qy)` (may branch) after them.
-  auto sweep = [&](int first, int stride, int last, auto&& arith, auto&& post)
-                   __attribute__((always_inline)) {
+  // BOUND: the bounding sweep's shorter chain (contract.h), whose scores take the inflated
+  // norm term `hs`.
+  auto sweep = [&](auto BOUNDc, float hs, int first, int stride, int last, auto&& arith,
+                   auto&& post) __attribute__((always_inline)) {
+    constexpr bool BOUND = decltype(BOUNDc)::value;
     if (first > last) return;
     const int nrows = (last - first) / stride + 1;
     BReg bufA[NB], bufB[NB];
@@ -283,7 +286,7 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
         o = c;
       } else {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o[k] = fmaf(hsq, p_n[k], c[k]);
+        for (int k = 0; k < 4; ++k) o[k] = fmaf(hs, p_n[k], c[k]);
       }
       return o;
     };
@@ -297,15 +300,15 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
       if constexpr (CT::kInitInChain) {
         if (!ncc) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k) init[k] = hsq * ninit[k];
+          for (int k = 0; k < 4; ++k) init[k] = hs * ninit[k];
         }
       }
       f4 acc[NAC];
-      CT::chain_t(A, cur, nxt, strip, nrb, plane, init, acc);
+      CT::template chain_t<BOUND>(A, cur, nxt, strip, nrb, plane, init, acc);
       const f4 ncur = ninit;
       ninit = load_norms(nqy, ntx);
       const auto res = arith(scores(), p_tx, p_qy);
-      CT::schedule();
+      CT::template schedule<BOUND>();
       __builtin_amdgcn_sched_barrier(0);
       if (have_prev) post(res, p_tx, p_qy);
 #pragma unroll
@@ -352,22 +355,38 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
 
   // ---- sweep 1: bounding lists over the rows inside every reference row's window (a
   //      subset of each window: its K-th smallest bounds the window's from above).  In 3D
-  //      it visits the reference's own slab only (still staged).
+  //      it visits the reference's own slab only (still staged).  A form with a shorter
+  //      bounding chain (contract.h) gives each distance up to kBoundRel (N_i + N_j) +
+  //      kBoundAbs away from the selecting sweep's; the sweep adds that margin (in its norm
+  //      terms), so its values bound the selecting sweep's distances of the same
+  //      candidates from above.  NCC keeps the selecting sweep's chain.
   {
     const int b_lo = max(0, ryw + s * a_max - r);
     const int b_hi = min(g.Hv - 1, ryw - r + wsp);
     const int p1 = g.p1_step;
-    sweep(b_lo + wave * p1, S * p1, b_hi,
-          [&](const f4& sc, int tx, int) __attribute__((always_inline)) {
-            f4 d;
+    auto sweep1 = [&](auto BOUNDc) __attribute__((always_inline)) {
+      constexpr bool BOUND = decltype(BOUNDc)::value;
+      const float grow = BOUND ? 1.f + CT::kBoundRel : 1.f;
+      const float base1 = BOUND ? fmaf(base, CT::kBoundRel, base) + CT::kBoundAbs : base;
+      sweep(BOUNDc, hsq * grow, b_lo + wave * p1, S * p1, b_hi,
+            [&](const f4& sc, int tx, int) __attribute__((always_inline)) {
+              f4 d;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) d[k] = col_mask(tx, k) ? fmaf(-2.f, sc[k], base) : INFINITY;
-            return d;
-          },
-          [&](const f4& d, int, int) __attribute__((always_inline)) {
+              for (int k = 0; k < 4; ++k)
+                d[k] = col_mask(tx, k) ? fmaf(-2.f, sc[k], base1) : INFINITY;
+              return d;
+            },
+            [&](const f4& d, int, int) __attribute__((always_inline)) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) lane_insert<TL>(sel.tl, d[k]);
-          });
+              for (int k = 0; k < 4; ++k) lane_insert<TL>(sel.tl, d[k]);
+            });
+    };
+    if constexpr (CT::kBoundChain) {
+      if (ncc) sweep1(std::false_type{});
+      else sweep1(std::true_type{});
+    } else {
+      sweep1(std::false_type{});
+    }
   }
 
   // ---- bound: reference p's values (its four lanes' lists in every wave) are merged by
@@ -447,7 +466,7 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
   // ---- sweep 2: select
   over_slabs([&]() __attribute__((always_inline)) {
     const int jbase = jofs + xs + 4 * gp;
-    sweep(qy_lo + wave, S, qy_hi,
+    sweep(std::false_type{}, hsq, qy_lo + wave, S, qy_hi,
           [&](const f4& sc, int tx, int qy) __attribute__((always_inline)) {
             const bool rok = row_ok(qy);
             Admit a;
