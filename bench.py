@@ -361,6 +361,10 @@ def quantile(v, q):
     return s[k]
 
 
+# sub-measurements of the default line besides the three gray512 forms
+SECTIONS = ["ncc", "nlm", "groups", "volumes", "rgbnir", "peaks", "batch", "serving", "cpu"]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -384,7 +388,15 @@ def main():
                     help="default line: timed calls of the 64-image batch per form (0: skip)")
     ap.add_argument("--serve-seconds-default", type=float, default=2.0,
                     help="default line: length of each serving rate's stream (0: skip)")
+    ap.add_argument("--sections", default=",".join(SECTIONS),
+                    help="default line: sub-measurements to run besides the three gray512 "
+                         "forms (comma-separated subset of " + ",".join(SECTIONS) + "; a "
+                         "profiler run can keep to the kernels it summarises)")
     args = ap.parse_args()
+    sections = set(x for x in args.sections.split(",") if x)
+    unknown = sections - set(SECTIONS)
+    if unknown:
+        ap.error(f"unknown sections {sorted(unknown)}")
     global WARM_S
     WARM_S = max(0.0, args.warm_ms) / 1e3
 
@@ -420,10 +432,13 @@ def main():
         results[prec] = run_form(bm, torch, img_t, sh, prec, args.steps, args.warmup)
     # the same workload ranked by normalized cross-correlation (BM_FLAG_NCC)
     ncc = {}
-    for prec in ["fp32", "fp16x3"]:
-        ncc[prec] = run_form(bm, torch, img_t, sh, prec, args.steps, args.warmup, bm.BM_FLAG_NCC)
-    nlm_res = run_nlm(bm, torch, img_t, sh, args.steps, args.warmup)
-    grp = run_groups(bm, torch, img_t, sh, results[args.precision][5][0], min(args.steps, 50))
+    if "ncc" in sections:
+        for prec in ["fp32", "fp16x3"]:
+            ncc[prec] = run_form(bm, torch, img_t, sh, prec, args.steps, args.warmup,
+                                 bm.BM_FLAG_NCC)
+    nlm_res = run_nlm(bm, torch, img_t, sh, args.steps, args.warmup) if "nlm" in sections else None
+    grp = (run_groups(bm, torch, img_t, sh, results[args.precision][5][0], min(args.steps, 50))
+           if "groups" in sections else None)
 
     prec = args.precision
     plan, wall, norm_ms, xc_ms, step_ms, _ = results[prec]
@@ -470,31 +485,40 @@ def main():
                     "p99_ms": quantile(sf, 0.99), "config": bm.bm_plan_config(pf)[0],
                     "roofline_frac": flops / xa / 1e12 / PEAK_TFLOPS[f]}
     out["forms"] = forms
-    nlm_ms, nlm_wall = nlm_res
-    nlm_flops = 2 * flops  # cross term + weighted patch sum, per in-window pair
-    out["nlm"] = {"value": sh.n_ref * args.steps / nlm_wall, "unit": "ref-patches/s",
-                  "ms_per_step": nlm_wall / args.steps * 1e3, "b": NLM_B,
-                  "kernel_ms": sum(nlm_ms) / len(nlm_ms),
-                  "roofline_frac": nlm_flops / (sum(nlm_ms) / len(nlm_ms) / 1e3) / 1e12 / PEAK_TFLOPS["fp32"]}
-    out["groups"] = grp
-    out["ncc_forms"] = {
-        f: {"value": pf.n_ref * args.steps / wf, "cross_topk_ms": sum(xf) / len(xf),
-            "p50_ms": quantile(sf, 0.5), "p99_ms": quantile(sf, 0.99)}
-        for f, (pf, wf, nf, xf, sf, _) in ncc.items()}
-    out["volumes"] = volumes(bm, synth, torch, max(3, args.steps // 20), 2)
-    rgb, rgb_outs = rgbnir_summary(bm, synth, torch, max(5, args.steps // 10))
-    out["rgbnir1024"] = rgb
+    if nlm_res is not None:
+        nlm_ms, nlm_wall = nlm_res
+        nlm_flops = 2 * flops  # cross term + weighted patch sum, per in-window pair
+        out["nlm"] = {"value": sh.n_ref * args.steps / nlm_wall, "unit": "ref-patches/s",
+                      "ms_per_step": nlm_wall / args.steps * 1e3, "b": NLM_B,
+                      "kernel_ms": sum(nlm_ms) / len(nlm_ms),
+                      "roofline_frac": nlm_flops / (sum(nlm_ms) / len(nlm_ms) / 1e3) / 1e12 /
+                      PEAK_TFLOPS["fp32"]}
+    if grp is not None:
+        out["groups"] = grp
+    if ncc:
+        out["ncc_forms"] = {
+            f: {"value": pf.n_ref * args.steps / wf, "cross_topk_ms": sum(xf) / len(xf),
+                "p50_ms": quantile(sf, 0.5), "p99_ms": quantile(sf, 0.99)}
+            for f, (pf, wf, nf, xf, sf, _) in ncc.items()}
+    if "volumes" in sections:
+        out["volumes"] = volumes(bm, synth, torch, max(3, args.steps // 20), 2)
+    rgb_outs = None
+    if "rgbnir" in sections:
+        rgb, rgb_outs = rgbnir_summary(bm, synth, torch, max(5, args.steps // 10))
+        out["rgbnir1024"] = rgb
     # measured attainable peaks beside the published ones
-    peaks = {f: bm.bm_peak_mfma(f, 0) for f in PEAK_TFLOPS}
-    peaks32 = {f: bm.bm_peak_mfma(f, 1) for f in PEAK_TFLOPS}
-    copy_gbps = bm.bm_peak_copy(1 << 30, 5)
-    out["peaks_measured"] = {"mfma_tflops": peaks, "mfma_32x32_tflops": peaks32,
-                             "copy_GBps": copy_gbps,
-                             "published": {"mfma_tflops": PEAK_TFLOPS, "hbm_GBps": 8000.0}}
-    out["roofline"]["peak_measured"] = peaks[prec]
-    out["roofline"]["frac_measured"] = achieved / peaks[prec]
-    for f in forms:
-        forms[f]["roofline_frac_measured"] = forms[f]["roofline_frac"] * PEAK_TFLOPS[f] / peaks[f]
+    if "peaks" in sections:
+        peaks = {f: bm.bm_peak_mfma(f, 0) for f in PEAK_TFLOPS}
+        peaks32 = {f: bm.bm_peak_mfma(f, 1) for f in PEAK_TFLOPS}
+        copy_gbps = bm.bm_peak_copy(1 << 30, 5)
+        out["peaks_measured"] = {"mfma_tflops": peaks, "mfma_32x32_tflops": peaks32,
+                                 "copy_GBps": copy_gbps,
+                                 "published": {"mfma_tflops": PEAK_TFLOPS, "hbm_GBps": 8000.0}}
+        out["roofline"]["peak_measured"] = peaks[prec]
+        out["roofline"]["frac_measured"] = achieved / peaks[prec]
+        for f in forms:
+            forms[f]["roofline_frac_measured"] = (forms[f]["roofline_frac"] * PEAK_TFLOPS[f] /
+                                                  peaks[f])
     counters = mfma_busy_from_profile(prec, w.name)
     if counters is not None:
         out["roofline"]["executed"] = counters
@@ -503,9 +527,9 @@ def main():
                    4.0 * (sh.height - sh.patch + 1) * (sh.width - sh.patch + 1)}
     out["norm"]["GBps"] = out["norm"]["algorithmic_bytes"] / (out["norm"]["ms"] * 1e6)
     # the uneven 64-image batch and the serving loop, short forms of their own workloads
-    if args.batch_steps > 0:
+    if args.batch_steps > 0 and "batch" in sections:
         out["batch64"] = batch_summary(bm, synth, torch, args.batch_steps)
-    if args.serve_seconds_default > 0:
+    if args.serve_seconds_default > 0 and "serving" in sections:
         pool = [w_ for _, w_ in synth.serving_requests(16, 100.0)]
         sweep = serve_sweep(bm, pool, SERVE_FORM, SERVE_QPS, args.serve_seconds_default,
                             args.clients)
@@ -523,15 +547,15 @@ def main():
                              "cross_topk_avg": xc_avg_s * 1e3}
     v32 = forms["fp32"]["value"]
     out["plain_fp32"] = {"value": v32, "speedup": value / v32}
-    if args.cpu_budget > 0:
+    if args.cpu_budget > 0 and "cpu" in sections:
         outs = {f: (r[5][0].cpu().numpy(), r[5][1].cpu().numpy()) for f, r in results.items()}
         out["cpu_baseline"] = cpu_baseline(w.image, sh, args.cpu_budget, outs,
-                                           {"rgbnir1024": rgb_outs})
+                                           {"rgbnir1024": rgb_outs} if rgb_outs else None)
         acc = out["cpu_baseline"].get("accuracy", {}).get("forms", {})
         out["accuracy"] = acc
         other = out["cpu_baseline"].get("accuracy_other", {}).get("rgbnir1024")
         if other:
-            rgb["accuracy"] = other
+            out["rgbnir1024"]["accuracy"] = other
         if prec in acc and not acc[prec]["within_rule"]:
             out["plain_fp32"]["speedup"] = None
             out["plain_fp32"]["note"] = f"{prec} is outside the 1e-4 rule on the sample"
