@@ -6,8 +6,9 @@
 //
 // One workgroup of 256 threads produces a kNormTY x kNormTX output tile (16 x 64: four
 // outputs per thread, one column and four rows).  Per channel it stages the
-// (TY+P-1) x (TX+P-1) input window in LDS (each thread keeps twelve loads in flight, in
-// rows of 32 consecutive columns, no index divisions), adds the horizontal P-tap sums of
+// (TY+P-1) x (TX+P-1) input window in LDS (each thread keeps the twelve loads of each of
+// up to four channels in flight together, in rows of 32 consecutive columns, no index
+// divisions), adds the horizontal P-tap sums of
 // squares of its columns into per-thread float64 accumulators (channels summed there),
 // and after the last channel forms the vertical P-tap sums.  Sums are direct (no prefix or
 // summed-area tables, whose rounding grows with the image) and carried in float64, so every
@@ -60,9 +61,12 @@ __device__ __forceinline__ void norm_tile(const float* __restrict__ img, float* 
   for (int k = 0; k < 8; ++k) hacc[k] = 0.0;
   float vmax = 0.f;
 
-  // channel c's loads are issued before channel c - 1's sums, so their latency overlaps
-  float v[4][3];
-  auto load = [&](int c) __attribute__((always_inline)) {
+  // The loads of up to kNormPre channels are in flight together from the start (channel
+  // c + kNormPre's are issued as channel c's registers free up), so one load latency is
+  // exposed per kNormPre channels instead of one per channel.
+  constexpr int kNormPre = 4;
+  float v[kNormPre][4][3];
+  auto load = [&](int c, float (&dst)[4][3]) __attribute__((always_inline)) {
     const float* plane = img + (size_t)c * g.H * g.W;
     const float cc = centers ? centers[c] : 0.f;
 #pragma unroll
@@ -71,36 +75,43 @@ __device__ __forceinline__ void norm_tile(const float* __restrict__ img, float* 
       for (int j = 0; j < 3; ++j) {
         const int y = oy0 + ly + 8 * i, x = ox0 + lx + 32 * j;
         const bool ok = (ly + 8 * i < rows) & (lx + 32 * j < cols) & (y < g.H) & (x < g.W);
-        v[i][j] = ok ? plane[(size_t)y * g.W + x] - cc : 0.f;
+        dst[i][j] = ok ? plane[(size_t)y * g.W + x] - cc : 0.f;
       }
   };
-  load(0);
-  for (int c = 0; c < g.C; ++c) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+  for (int u = 0; u < kNormPre; ++u)
+    if (u < g.C) load(u, v[u]);
+  for (int c0 = 0; c0 < g.C; c0 += kNormPre) {
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        float x = v[i][j];
-        if (g.round_bf16) x = bf16_split_value(x);
-        vmax = fmaxf(vmax, fabsf(x));
-        if ((ly + 8 * i < kStageRows) & (lx + 32 * j < kStageRS))
-          sh.tile[ly + 8 * i][lx + 32 * j] = x;
-      }
-    __syncthreads();
-    if (c + 1 < g.C) load(c + 1);
+    for (int u = 0; u < kNormPre; ++u) {
+      const int c = c0 + u;
+      if (c >= g.C) break;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int r = hr + 4 * k;
-      if (r < rows) {
-        double s = 0.0;
-        for (int m = 0; m < g.P; ++m) {
-          const double x = (double)sh.tile[r][hc + m];
-          s = fma(x, x, s);
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          float x = v[u][i][j];
+          if (g.round_bf16) x = bf16_split_value(x);
+          vmax = fmaxf(vmax, fabsf(x));
+          if ((ly + 8 * i < kStageRows) & (lx + 32 * j < kStageRS))
+            sh.tile[ly + 8 * i][lx + 32 * j] = x;
         }
-        hacc[k] += s;
+      __syncthreads();
+      if (c + kNormPre < g.C) load(c + kNormPre, v[u]);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int r = hr + 4 * k;
+        if (r < rows) {
+          double s = 0.0;
+          for (int m = 0; m < g.P; ++m) {
+            const double x = (double)sh.tile[r][hc + m];
+            s = fma(x, x, s);
+          }
+          hacc[k] += s;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k)
@@ -129,14 +140,15 @@ __device__ __forceinline__ void norm_tile(const float* __restrict__ img, float* 
   }
 }
 
-__global__ void __launch_bounds__(256)
+// four workgroups (16 waves) per compute unit: registers held to 128
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 norm_box_kernel(const float* __restrict__ img, float* __restrict__ out, NormGeom g,
                 const float* __restrict__ centers, float* __restrict__ amax) {
   __shared__ NormLds sh;
   norm_tile(img, out, g, centers, amax, blockIdx.x, blockIdx.y, sh);
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 norm_box_batch_kernel(const BatchNorm* __restrict__ items, int n, unsigned* __restrict__ counters,
                       int n_counters) {
   __shared__ NormLds sh;
