@@ -275,13 +275,15 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
     f4 ninit = load_norms(qy, 0);
     // scores of the previous tile: Euclidean <X_i, X_j> - ||X_j||^2 / 2 (float32: started
     // from the norm term in the chain; split forms: added here, one fused multiply-add),
-    // NCC <X_i, X_j> / ||X_j||
+    // NCC <X_i, X_j> / ||X_j|| (the hardware reciprocal square root, within an ulp or two:
+    // far inside the NCC tolerance; equal outputs of distinct keys are re-sorted by index
+    // at the end)
     auto scores = [&]() __attribute__((always_inline)) {
       const f4 c = CT::combine(accp);
       f4 o;
       if (ncc) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) o[k] = p_n[k] > 0.f ? c[k] * (isq / sqrtf(p_n[k])) : 0.f;
+        for (int k = 0; k < 4; ++k) o[k] = p_n[k] > 0.f ? c[k] * (isq * rsqrtf(p_n[k])) : 0.f;
       } else if constexpr (CT::kInitInChain) {
         o = c;
       } else {
@@ -511,6 +513,9 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
     int fl = 0;
     for (int w = 0; w < S; ++w) fl |= reinterpret_cast<const int*>(bufs + w * wst + (size_t)16 * CAP * 8)[0];
     any_flushed = (__builtin_amdgcn_readfirstlane(fl) & kFlushedBit) != 0;
+    // every wave has read the flags before a flush below clears its counters (a wave
+    // reading a cleared flag would take the other path)
+    __syncthreads();
   }
   if (!any_flushed) {
     const size_t wstride = (size_t)16 * CAP * 8 + 64;
