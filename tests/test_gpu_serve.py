@@ -83,6 +83,42 @@ def test_serving_mix_equals_single_and_oracle(gpu):
         bm.bm_server_destroy(srv)
 
 
+def test_serving_config5_scale(gpu):
+    """Requests at the serving workload's scale in one mix: a 2048 x 2048 x 4 image, a
+    256 x 256 one and mid-size ones of 1..4 channels, bfloat16 split (the serving form) and
+    the other forms; each result equals bm_match bit for bit, and sampled references
+    (border rows included) meet the oracle's rule."""
+    banner("serving at scale: 2048 x 2048 x 4 and 256 x 256 in one mix")
+    bm = ensure_built()
+    shapes = [(2048, 2048, 4, "bf16x4"), (256, 256, 1, "bf16x4"), (1024, 700, 3, "bf16x4"),
+              (517, 1301, 2, "fp16x3"), (300, 300, 1, "fp32"), (256, 512, 4, "bf16x4")]
+    reqs = []
+    for i, (H, W, C, prec) in enumerate(shapes):
+        x = (synth.gray_voronoi(300 + i, H, W, 50.0) if C == 1 else
+             synth.multichannel_voronoi(300 + i, H, W, C, 50.0, nir=(C == 4)))
+        reqs.append((x, prec))
+    srv = bm.bm_server_create(2 << 30, max_inflight=8, max_queue=64)
+    try:
+        tickets = [(bm.bm_submit(srv, desc_for(bm, x, prec), x), desc_for(bm, x, prec))
+                   for x, prec in reqs]
+        rng = np.random.default_rng(6)
+        for (x, prec), (t, d) in zip(reqs, tickets):
+            n_ref = bm.cached_plan(d).n_ref
+            idx, dist, _ = wait(bm, srv, t, n_ref, d.k, timeout=120.0)
+            sidx, sdist = single(bm, x, d)
+            assert np.array_equal(idx, sidx), (x.shape, prec)
+            assert np.array_equal(dist.view(np.uint32), sdist.view(np.uint32)), (x.shape, prec)
+            nrx = (x.shape[2] - d.patch) // d.stride + 1
+            refs = np.unique(np.concatenate([rng.choice(n_ref, size=min(40, n_ref), replace=False),
+                                             np.arange(min(8, nrx)), n_ref - 1 - np.arange(min(8, nrx))]))
+            rep = parity.check(x, d.patch, d.stride, d.window, d.k, idx[refs], dist[refs],
+                               refs=refs, tol=1e-4)
+            print(x.shape, prec, rep.summary())
+            assert rep.tolerant_mismatch == 0 and rep.order_violations == 0, rep.summary()
+    finally:
+        bm.bm_server_destroy(srv)
+
+
 def test_serving_alone_equals_in_mix(gpu):
     banner("serving: one request alone and inside a mix")
     bm = ensure_built()
