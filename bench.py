@@ -19,8 +19,9 @@ committed counter summary when it matches the current sources.  The same line ca
 short forms of the other workloads: `rgbnir1024` (the split-precision workload, 1024 x
 1024 x 4 with joint 8 x 8 x 4 patches, every form, with its accuracy), `batch64` (the
 64-image uneven batch, one bm_match_batch call per step in each form, and the same images
-as 64 bm_match calls), `serving` (Poisson streams through bm_submit / bm_poll at two request rates, bfloat16
-split; `latency_ms` then holds the request latency of the lower rate), and `cpu_baseline`
+as 64 bm_match calls), `serving` (Poisson streams through bm_submit / bm_poll at two
+request rates, bfloat16 split; `latency_ms` then holds the request latency of the lower
+rate), and `cpu_baseline`
 (the FP64 oracle on this host: one core on a bounded sample, all cores on the whole
 image) with `accuracy`, the error of every form against the oracle on a seeded sample.
 
