@@ -11,8 +11,9 @@ Output: one JSON line.  Every precision form is timed (plain float32, bfloat16 s
 float16 split); `value` is ref-patches/s of the reported form (default: the bfloat16 split,
 whose distances are exactly those of the image rounded to 16 significant bits, the form
 of the serving workload) over the timed region with the inputs already in HBM, and
-`plain_fp32` gives the plain float32 form beside it.  `roofline` covers the dominant kernel (the cross-term kernel of
-the reported form), timed with HIP events on its own launch stream, against the published
+`plain_fp32` gives the plain float32 form beside it.  `roofline` covers the dominant
+kernel (the cross-term kernel of the reported form), timed with HIP events on its own
+launch stream, against the published
 matrix peak and the peak measured in the same run (`peaks_measured`: a matrix-op loop per
 form and a streaming copy); `executed` adds the matrix/vector pipe utilisation from the
 committed counter summary when it matches the current sources.  The same line carries
