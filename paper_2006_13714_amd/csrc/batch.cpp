@@ -1,7 +1,9 @@
 // Uneven batch: many images of different shapes, plans and precisions in as few launches as
 // the kernels allow — one batch norm launch, then one persistent cross-term launch per
 // (precision, K class, tile columns, channel tier) group of the specialised kernel, plus a
-// regular launch per image whose shape only the generic kernel covers.
+// regular launch per image whose shape only the generic kernel covers or whose reference
+// blocks alone fill the device several times over (the persistent launch pays off for the
+// images whose single launches would leave most of the device idle).
 //
 // Host side: form the groups, order each group's images by decreasing cost per reference
 // block (largest contraction first, so the items handed out last are the cheapest), lay out
@@ -165,12 +167,16 @@ bm_status run_batch(const BatchEntry* e, int n, void* d_header, hipStream_t s) {
       return fail(BM_EINVAL, "batch entry %d: float16 plan without a max map slot", b);
   }
 
-  // ---- groups of the persistent kernel; the rest run the generic kernel one by one
+  // ---- groups of the persistent kernel; the rest run their own launches one by one: the
+  //      generic kernel's images, and images whose reference blocks alone fill the device
+  //      several times over (kSingleBlocksPerCu per compute unit), which then run the
+  //      single-image kernel with their own tuned configuration instead of the group's
   std::map<std::tuple<int, int, int, int>, Group> groups;
   std::vector<int> generic;
+  constexpr int kSingleBlocksPerCu = 4;
   for (int b = 0; b < n; ++b) {
     const bm_plan_s& p = *e[b].plan;
-    if (!p.geom.fast) {
+    if (!p.geom.fast || p.geom.nwg_total >= kSingleBlocksPerCu * n_cu) {
       generic.push_back(b);
       continue;
     }
