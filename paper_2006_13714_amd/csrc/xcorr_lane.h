@@ -282,8 +282,16 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
       const f4 c = CT::combine(accp);
       f4 o;
       if (ncc) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) o[k] = p_n[k] > 0.f ? c[k] * (isq * rsqrtf(p_n[k])) : 0.f;
+        // the 16 lanes of a row share candidates 4 g .. 4 g + 3: lane k < 4 of the row forms
+        // candidate k's factor (every lane computes one), and a row broadcast hands it on
+        const int own = p16 & 3;
+        const float nk = own == 0 ? p_n[0] : (own == 1 ? p_n[1] : (own == 2 ? p_n[2] : p_n[3]));
+        const float rk = nk > 0.f ? isq * rsqrtf(nk) : 0.f;
+        const int ri = __float_as_int(rk);
+        o[0] = c[0] * __int_as_float(__builtin_amdgcn_update_dpp(0, ri, 0x150, 0xF, 0xF, false));
+        o[1] = c[1] * __int_as_float(__builtin_amdgcn_update_dpp(0, ri, 0x151, 0xF, 0xF, false));
+        o[2] = c[2] * __int_as_float(__builtin_amdgcn_update_dpp(0, ri, 0x152, 0xF, 0xF, false));
+        o[3] = c[3] * __int_as_float(__builtin_amdgcn_update_dpp(0, ri, 0x153, 0xF, 0xF, false));
       } else if constexpr (CT::kInitInChain) {
         o = c;
       } else {
