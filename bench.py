@@ -18,7 +18,10 @@ matrix peak and the peak measured in the same run (`peaks_measured`: a matrix-op
 form and a streaming copy); `executed` adds the matrix/vector pipe utilisation from the
 committed counter summary when it matches the current sources.  The same line carries
 short forms of the other workloads: `rgbnir1024` (the split-precision workload, 1024 x
-1024 x 4 with joint 8 x 8 x 4 patches, every form, with its accuracy), `batch64` (the
+1024 x 4 with joint 8 x 8 x 4 patches, every form, with its accuracy), `shapes` (the
+paper's single-channel runtime setup, 6 x 6 patches at stride 1 in a 30 x 30 window, every
+form with its accuracy, and a window outside the specialised envelope on the generic
+float32 kernel), `batch64` (the
 64-image uneven batch, one bm_match_batch call per step in each form, and the same images
 as 64 bm_match calls), `serving` (Poisson streams through bm_submit / bm_poll at two
 request rates, bfloat16 split; `latency_ms` then holds the request latency of the lower
@@ -365,7 +368,8 @@ def quantile(v, q):
 
 
 # sub-measurements of the default line besides the three gray512 forms
-SECTIONS = ["ncc", "nlm", "groups", "volumes", "rgbnir", "peaks", "batch", "serving", "cpu"]
+SECTIONS = ["ncc", "nlm", "groups", "volumes", "rgbnir", "shapes", "peaks", "batch", "serving",
+            "cpu"]
 
 
 def main():
@@ -509,6 +513,10 @@ def main():
     if "rgbnir" in sections:
         rgb, rgb_outs = rgbnir_summary(bm, synth, torch, max(5, args.steps // 10))
         out["rgbnir1024"] = rgb
+    shape_outs = None
+    if "shapes" in sections:
+        shp, shape_outs = shapes_summary(bm, synth, torch, img_t, w.image, max(5, args.steps // 10))
+        out["shapes"] = shp
     # measured attainable peaks beside the published ones
     if "peaks" in sections:
         peaks = {f: bm.bm_peak_mfma(f, 0) for f in PEAK_TFLOPS}
@@ -552,17 +560,53 @@ def main():
     out["plain_fp32"] = {"value": v32, "speedup": value / v32}
     if args.cpu_budget > 0 and "cpu" in sections:
         outs = {f: (r[5][0].cpu().numpy(), r[5][1].cpu().numpy()) for f, r in results.items()}
-        out["cpu_baseline"] = cpu_baseline(w.image, sh, args.cpu_budget, outs,
-                                           {"rgbnir1024": rgb_outs} if rgb_outs else None)
+        extra = {}
+        if rgb_outs:
+            extra["rgbnir1024"] = rgb_outs
+        if shape_outs:
+            extra["paper_setup"] = shape_outs
+        out["cpu_baseline"] = cpu_baseline(w.image, sh, args.cpu_budget, outs, extra)
         acc = out["cpu_baseline"].get("accuracy", {}).get("forms", {})
         out["accuracy"] = acc
-        other = out["cpu_baseline"].get("accuracy_other", {}).get("rgbnir1024")
-        if other:
-            out["rgbnir1024"]["accuracy"] = other
+        other = out["cpu_baseline"].get("accuracy_other", {})
+        if "rgbnir1024" in other:
+            out["rgbnir1024"]["accuracy"] = other["rgbnir1024"]
+        if "paper_setup" in other:
+            out["shapes"]["paper_setup"]["accuracy"] = other["paper_setup"]
         if prec in acc and not acc[prec]["within_rule"]:
             out["plain_fp32"]["speedup"] = None
             out["plain_fp32"]["note"] = f"{prec} is outside the 1e-4 rule on the sample"
     print(json.dumps(out), flush=True)
+
+
+def shapes_summary(bm, synth, torch, img_t, img, steps):
+    """Two more shapes on the gray512 image: the paper's single-channel runtime setup
+    (6 x 6 patches, stride 1, 30 x 30 window, Sec. V-A; K = 16) in every form, and a shape
+    outside the specialised kernel's envelope (8 x 8 patches, stride 3, 61 x 61 window:
+    3 s + Wn = 70 > 48), which runs the generic float32 kernel.  Returns the summary and the
+    paper setup's outputs (for accuracy)."""
+    res = {}
+    outs = {}
+    for name, (P, s_, Wn, forms) in {"paper_setup": (6, 1, 30, ["fp32", "bf16x4", "fp16x3"]),
+                                     "generic_fp32": (8, 3, 61, ["fp32"])}.items():
+        sh = synth.BMShape(512, 512, 1, P, s_, Wn, 16)
+        pairs = pair_count(sh.height, sh.width, P, s_, Wn)
+        flops = 2.0 * P * P * pairs
+        entry = {"height": 512, "width": 512, "channels": 1, "patch": P, "stride": s_,
+                 "window": Wn, "k": 16, "n_ref": sh.n_ref, "pairs": pairs, "forms": {}}
+        for prec in forms:
+            plan, wall, norm_ms, xc_ms, step_ms, (idx, dist) = run_form(
+                bm, torch, img_t, sh, prec, steps, 2)
+            xa = sum(xc_ms) / len(xc_ms) / 1e3
+            entry["forms"][prec] = {"value": sh.n_ref * steps / wall,
+                                    "ms_per_step": wall / steps * 1e3,
+                                    "cross_topk_ms": xa * 1e3,
+                                    "config": bm.bm_plan_config(plan)[0],
+                                    "roofline_frac": flops / xa / 1e12 / PEAK_TFLOPS[prec]}
+            if name == "paper_setup":
+                outs[prec] = (idx.cpu().numpy(), dist.cpu().numpy())
+        res[name] = entry
+    return res, (img, synth.BMShape(512, 512, 1, 6, 1, 30, 16), outs)
 
 
 def rgbnir_summary(bm, synth, torch, steps):
