@@ -314,12 +314,17 @@ __device__ __forceinline__ void lane_block(const float* __restrict__ img,
         }
       }
       f4 acc[NAC];
+      // split forms: the waves issuing a tile's matrix chain (with the previous tile's score
+      // arithmetic interleaved) go first, ahead of waves in their buffer writes, merges or
+      // staging, so the matrix pipe is fed while those wait (2% on one-channel blocks)
+      if constexpr (CT::kSplit) __builtin_amdgcn_s_setprio(1);
       CT::template chain_t<BOUND>(A, cur, nxt, strip, nrb, plane, init, acc);
       const f4 ncur = ninit;
       ninit = load_norms(nqy, ntx);
       const auto res = arith(scores(), p_tx, p_qy);
       CT::template schedule<BOUND>();
       __builtin_amdgcn_sched_barrier(0);
+      if constexpr (CT::kSplit) __builtin_amdgcn_s_setprio(0);
       if (have_prev) post(res, p_tx, p_qy);
 #pragma unroll
       for (int q = 0; q < NAC; ++q) accp[q] = acc[q];
