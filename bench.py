@@ -385,6 +385,8 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 64 MiB device copy (counter calibration)")
     ap.add_argument("--workload", default="gray512", choices=["gray512", "batch64", "serving"])
+    ap.add_argument("--batch-max-side", type=int, default=1024,
+                    help="batch64: largest image side (sides uniform in [128, this])")
     ap.add_argument("--qps", default="50,200,500,1000,2000",
                     help="serving: comma-separated request rates")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
@@ -711,7 +713,7 @@ def mfma_busy_from_profile(prec: str, workload: str):
 def bench_batch(args, bm, synth, torch):
     """The 64-image uneven workload: one bm_match_batch call per step."""
     import numpy as np
-    ws = synth.uneven_batch(64)
+    ws = synth.uneven_batch(64, max_side=args.batch_max_side)
     ts = [torch.from_numpy(w.image).to("cuda:0") for w in ws]
     n_ref = sum(w.shape.n_ref for w in ws)
     flops = sum(2.0 * w.shape.patch ** 2 * w.shape.channels *
@@ -762,7 +764,7 @@ def bench_batch(args, bm, synth, torch):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[prec], "data": "synthetic",
         "config": {"workload": "uneven_batch64", "images": len(ws), "n_ref": n_ref,
-                   "precision": prec, "seed0": 1000},
+                   "precision": prec, "seed0": 1000, "sides": [128, args.batch_max_side]},
         "latency_ms": {"p50": forms[prec]["batch"]["p50_ms"], "p99": forms[prec]["batch"]["p99_ms"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec],
                      "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,

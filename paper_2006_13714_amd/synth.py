@@ -229,18 +229,20 @@ def multimodal6() -> Workload:
                     {"field": "voronoi base x gain U[0.7, 1.3] per plane", "sigma255": 25})
 
 
-def uneven_batch(n_images: int = 64, seed0: int = 1000):
-    """Batch of images with independent random sides in [128, 1024], C in {1,3}, P in {6,8}.
+def uneven_batch(n_images: int = 64, seed0: int = 1000, min_side: int = 128,
+                 max_side: int = 1024):
+    """Batch of images with independent random sides in [min_side, max_side] (default
+    [128, 1024]), C in {1,3}, P in {6,8}.
 
-    Image i uses seed ``seed0 + i``. Draw order per image: H, W (integers in [128, 1024]),
+    Image i uses seed ``seed0 + i``. Draw order per image: H, W (integers in the side range),
     C (1 or 3 with p = 0.5), P (6 or 8 with p = 0.5), then the image content (Voronoi base,
     colour gains for C=3, noise sigma 50/255). Window 39x39, stride 3, K=16.
     """
     out = []
     for i in range(n_images):
         rng = np.random.default_rng(seed0 + i)
-        H = int(rng.integers(128, 1025))
-        W = int(rng.integers(128, 1025))
+        H = int(rng.integers(min_side, max_side + 1))
+        W = int(rng.integers(min_side, max_side + 1))
         C = 1 if rng.random() < 0.5 else 3
         P = 6 if rng.random() < 0.5 else 8
         content_seed = int(rng.integers(0, 2**31 - 1))
