@@ -410,7 +410,7 @@ def main():
     WARM_S = max(0.0, args.warm_ms) / 1e3
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; multi-GPU runs are not part of it "
+        print("bench.py: measures one GPU only; multi-GPU runs are not part of it "
               "(the repository's design notes describe how the path would shard)", file=sys.stderr)
         sys.exit(2)
 

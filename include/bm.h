@@ -49,7 +49,7 @@ typedef int32_t bm_status;
 #define BM_EBUSY (-5)       /* bm_submit: admission refused (budget or slots)         */
 #define BM_ENOTFOUND (-6)   /* unknown ticket                                          */
 #define BM_ECANCELED (-7)   /* ticket was cancelled                                    */
-#define BM_ENOTSUP (-8)     /* valid request outside what this build supports          */
+#define BM_ENOTSUP (-8)     /* valid request outside what the library supports         */
 
 /* Arithmetic of the cross term <X_i, X_j>.  Norms and the distance assembly are float32
  * in every form.  The split forms write x = hi + lo (hi = round(x), lo = round(x - hi)) and
